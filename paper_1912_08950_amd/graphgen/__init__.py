@@ -1,0 +1,191 @@
+"""Seeded synthetic input graphs (G(n,q) and R-MAT) as symmetric sorted CSR.
+
+This module draws inputs only; it holds none of the compression method's
+arithmetic.  Both the GPU path and the CPU oracle consume what it returns.
+The native part (``graphgen.c``) is built with gcc + OpenMP into
+``libslimgen.so`` next to this file; output does not depend on thread count.
+
+Workload recipes (the paper's real graphs are not available; these synthetic
+graphs stand in for them):
+
+* ``er(n, avg_degree, seed)`` -- G(n, q) with q = avg_degree / (n - 1).
+* ``rmat(scale, edge_factor, seed)`` -- R-MAT with a,b,c,d = .57,.19,.19,.05,
+  edge_factor * 2^scale directed samples, ids through a seeded bijection of
+  [0, 2^scale), symmetrized, self-loops and duplicates removed.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "graphgen.c")
+_LIB = os.path.join(_HERE, "libslimgen.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile libslimgen.so with gcc (-O3 -fopenmp)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O3", "-march=x86-64-v2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
+               "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB)
+    i64p = ctypes.POINTER(ctypes.POINTER(ctypes.c_int64))
+    u32p = ctypes.POINTER(ctypes.POINTER(ctypes.c_uint32))
+    u64 = ctypes.c_uint64
+    lib.sg_gen_er.argtypes = [u64, ctypes.c_double, u64, i64p, u32p, ctypes.POINTER(u64)]
+    lib.sg_gen_er.restype = ctypes.c_int
+    lib.sg_gen_rmat.argtypes = [ctypes.c_int, u64, u64, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_int, u64, i64p, u32p,
+                                ctypes.POINTER(u64)]
+    lib.sg_gen_rmat.restype = ctypes.c_int
+    lib.sg_pairs_csr.argtypes = [u64, ctypes.c_void_p, ctypes.c_void_p, u64, i64p, u32p,
+                                 ctypes.POINTER(u64)]
+    lib.sg_pairs_csr.restype = ctypes.c_int
+    lib.sg_copy_free.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32),
+                                 u64, u64, ctypes.c_void_p, ctypes.c_void_p]
+    lib.sg_copy_free.restype = None
+    lib.sg_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+@dataclass
+class CSR:
+    """Undirected simple graph: symmetric CSR, sorted rows, no self-loops."""
+    row_off: np.ndarray  # int64 [n+1]
+    col: np.ndarray      # uint32 [nnz]
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return int(self.row_off.shape[0] - 1)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+    @property
+    def m(self) -> int:
+        return self.nnz // 2
+
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.row_off)
+
+
+def _collect(rc, n, ro_p, col_p, nnz, name) -> CSR:
+    lib = _load()
+    if rc != 0:
+        raise RuntimeError(f"graph generator failed (rc={rc}) for {name}")
+    nnz = int(nnz.value)
+    row_off = np.empty(n + 1, dtype=np.int64)
+    col = np.empty(nnz, dtype=np.uint32)
+    lib.sg_copy_free(ro_p, col_p, n, nnz, row_off.ctypes.data, col.ctypes.data)
+    return CSR(row_off, col, name)
+
+
+def er(n: int, avg_degree: float, seed: int) -> CSR:
+    """G(n, q) with q = avg_degree / (n - 1)."""
+    lib = _load()
+    ro_p = ctypes.POINTER(ctypes.c_int64)()
+    col_p = ctypes.POINTER(ctypes.c_uint32)()
+    nnz = ctypes.c_uint64(0)
+    rc = lib.sg_gen_er(n, float(avg_degree), seed, ctypes.byref(ro_p), ctypes.byref(col_p),
+                       ctypes.byref(nnz))
+    return _collect(rc, n, ro_p, col_p, nnz, f"er_n{n}_d{avg_degree:g}_s{seed}")
+
+
+def rmat(scale: int, edge_factor: float, seed: int, n: int | None = None,
+         abc=(0.57, 0.19, 0.19), permute: bool = True, samples: int | None = None) -> CSR:
+    """R-MAT graph; n defaults to 2^scale (endpoints >= n are rejected)."""
+    lib = _load()
+    nn = (1 << scale) if n is None else int(n)
+    if samples is None:
+        samples = int(round(edge_factor * nn))
+    ro_p = ctypes.POINTER(ctypes.c_int64)()
+    col_p = ctypes.POINTER(ctypes.c_uint32)()
+    nnz = ctypes.c_uint64(0)
+    rc = lib.sg_gen_rmat(scale, nn, samples, abc[0], abc[1], abc[2], 1 if permute else 0, seed,
+                         ctypes.byref(ro_p), ctypes.byref(col_p), ctypes.byref(nnz))
+    return _collect(rc, nn, ro_p, col_p, nnz, f"rmat_s{scale}_ef{edge_factor:g}_s{seed}")
+
+
+def from_pairs(n: int, pairs, name: str = "pairs") -> CSR:
+    """CSR of the undirected simple graph spanned by a list of (u, v) pairs."""
+    lib = _load()
+    arr = np.asarray(pairs, dtype=np.uint32).reshape(-1, 2)
+    pu = np.ascontiguousarray(arr[:, 0])
+    pv = np.ascontiguousarray(arr[:, 1])
+    ro_p = ctypes.POINTER(ctypes.c_int64)()
+    col_p = ctypes.POINTER(ctypes.c_uint32)()
+    nnz = ctypes.c_uint64(0)
+    rc = lib.sg_pairs_csr(n, pu.ctypes.data, pv.ctypes.data, len(pu), ctypes.byref(ro_p),
+                          ctypes.byref(col_p), ctypes.byref(nnz))
+    return _collect(rc, n, ro_p, col_p, nnz, name)
+
+
+# ---- small named families used by tests ---------------------------------
+
+def complete(n: int) -> CSR:
+    return from_pairs(n, [(u, v) for u in range(n) for v in range(u + 1, n)], f"K{n}")
+
+
+def path(n: int) -> CSR:
+    return from_pairs(n, [(i, i + 1) for i in range(n - 1)], f"P{n}")
+
+
+def cycle(n: int) -> CSR:
+    return from_pairs(n, [(i, (i + 1) % n) for i in range(n)], f"C{n}")
+
+
+def star(n: int) -> CSR:
+    return from_pairs(n, [(0, i) for i in range(1, n)], f"S{n}")
+
+
+def grid(r: int, c: int) -> CSR:
+    pairs = []
+    for i in range(r):
+        for j in range(c):
+            v = i * c + j
+            if j + 1 < c:
+                pairs.append((v, v + 1))
+            if i + 1 < r:
+                pairs.append((v, v + c))
+    return from_pairs(r * c, pairs, f"grid{r}x{c}")
+
+
+def complete_bipartite(a: int, b: int) -> CSR:
+    return from_pairs(a + b, [(i, a + j) for i in range(a) for j in range(b)], f"K{a},{b}")
+
+
+def friendship(k: int) -> CSR:
+    """k triangles sharing the single vertex 0 (edge-disjoint triangles)."""
+    pairs = []
+    for t in range(k):
+        x, y = 1 + 2 * t, 2 + 2 * t
+        pairs += [(0, x), (0, y), (x, y)]
+    return from_pairs(2 * k + 1, pairs, f"F{k}")
+
+
+def empty(n: int) -> CSR:
+    return CSR(np.zeros(n + 1, dtype=np.int64), np.zeros(0, dtype=np.uint32), f"E{n}")
+
+
+def num_threads() -> int:
+    return int(_load().sg_num_threads())

@@ -1,0 +1,334 @@
+"""Pins of the CPU oracle against facts the paper and mathematics fix.
+
+Nothing here compares the oracle with itself: every check is brute force on
+tiny inputs, a closed form, an exact expectation, a special case with a
+textbook answer, a published known-answer vector, or a number the paper
+prints (Table `tab:tcv`).
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1912_08950_amd import graphgen as gg
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+# ----------------------------------------------------------------- helpers
+
+def dense(g):
+    a = np.zeros((g.n, g.n), dtype=np.int64)
+    for r in range(g.n):
+        a[r, g.col[g.row_off[r]:g.row_off[r + 1]]] = 1
+    return a
+
+
+def brute_triangles(g):
+    """O(n^3) enumeration of {a<b<c} with all three edges present."""
+    a = dense(g)
+    return {(x, y, z) for x, y, z in itertools.combinations(range(g.n), 3)
+            if a[x, y] and a[x, z] and a[y, z]}
+
+
+def edge_set(row_off, col):
+    s = set()
+    for r in range(len(row_off) - 1):
+        for c in col[row_off[r]:row_off[r + 1]]:
+            s.add((r, int(c)))
+    return s
+
+
+def undirected(row_off, col):
+    return {(r, c) for (r, c) in edge_set(row_off, col) if r < c}
+
+
+def is_valid_csr(n, row_off, col):
+    g = gg.CSR(np.asarray(row_off, dtype=np.int64), np.asarray(col, dtype=np.uint32))
+    return len(row_off) == n + 1 and O.validate(g) == 0
+
+
+def trace_triangles(row_off, col, n):
+    """Triangle count of a CSR from trace(A^3)/6 (dense numpy)."""
+    g = gg.CSR(np.asarray(row_off), np.asarray(col))
+    a = dense(g).astype(np.float64)
+    return int(round(np.trace(a @ a @ a) / 6.0))
+
+
+CFG1 = dict(n=2000, d=16.0, seed=1)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return gg.er(CFG1["n"], CFG1["d"], CFG1["seed"])
+
+
+# ------------------------------------------------------------ Philox KAT
+
+def test_philox_known_answer_vectors():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        assert O.philox4x32_10(v[0:4], v[4:6]) == v[6:10]
+
+
+def test_threshold_endpoints():
+    assert O.threshold(0.0) == 0
+    assert O.threshold(1.0) == 2**32
+    assert O.threshold(0.5) == 2**31
+    assert O.threshold(0.25) == 2**30
+    for bad in (-0.1, 1.5, float("nan"), float("inf")):
+        with pytest.raises(ValueError):
+            O.threshold(bad)
+
+
+# ------------------------------------------------------- triangle listing
+
+@pytest.mark.parametrize("n,q,seed", [(12, 0.5, 1), (25, 0.3, 2), (40, 0.2, 3), (40, 0.6, 4),
+                                      (30, 0.9, 5)])
+def test_listing_matches_brute_force(n, q, seed):
+    g = gg.er(n, q * (n - 1), seed)
+    got = {tuple(int(x) for x in t) for t in O.list_triangles(g)}
+    assert len(got) == len(O.list_triangles(g))  # each triangle exactly once
+    assert got == brute_triangles(g)
+
+
+@pytest.mark.parametrize("n", range(3, 13))
+def test_complete_graph_triangles(n):
+    g = gg.complete(n)
+    assert len(O.list_triangles(g)) == math.comb(n, 3)
+
+
+def test_k4_small_case():
+    g = gg.complete(4)
+    _, _, st = O.triangle_reduce(g, 0.0, 1)
+    assert st["T"] == 4 and st["m_in"] == 6
+
+
+@pytest.mark.parametrize("g", [gg.path(50), gg.star(40), gg.grid(7, 9), gg.complete_bipartite(6, 9),
+                               gg.cycle(20), gg.cycle(4), gg.empty(5)], ids=lambda g: g.name)
+@pytest.mark.parametrize("p", [0.0, 0.5, 1.0])
+def test_triangle_free_families_unchanged(g, p):
+    ro, col, st = O.triangle_reduce(g, p, 7)
+    assert st["T"] == 0 and st["selected"] == 0 and st["deleted"] == 0
+    assert np.array_equal(ro, g.row_off) and np.array_equal(col, g.col)
+
+
+def test_cycle_c3_is_a_triangle():
+    assert len(O.list_triangles(gg.cycle(3))) == 1
+
+
+def test_per_vertex_counts_sum_to_3T(cfg1):
+    """Triangles per vertex (the Table `tab:tcv` quantity, summed) = 3T."""
+    tris = O.list_triangles(cfg1)
+    per_vertex = np.bincount(tris.ravel(), minlength=cfg1.n)
+    assert per_vertex.sum() == 3 * len(tris)
+    a = dense(cfg1).astype(np.float64)
+    a2 = a @ a
+    assert np.array_equal(per_vertex, (np.sum(a2 * a, axis=1) / 2).round().astype(np.int64))
+
+
+# ------------------------------------------------ G(n,q) triangle counts
+
+def _er_T_mean_var(n, q):
+    c3 = math.comb(n, 3)
+    mean = c3 * q**3
+    var = c3 * (q**3 - q**6) + 3 * c3 * (n - 3) * (q**5 - q**6)
+    return mean, var
+
+
+def test_gnq_expected_triangles(cfg1):
+    """E[T] = C(n,3) q^3 for G(n,q); 682.67 for n=2000, q=16/1999."""
+    n, q = CFG1["n"], CFG1["d"] / (CFG1["n"] - 1)
+    mean, var = _er_T_mean_var(n, q)
+    assert abs(mean - 682.67) < 0.01
+    t1 = len(O.list_triangles(cfg1))
+    assert abs(t1 - mean) < 4 * math.sqrt(var)
+    ts = [len(O.list_triangles(gg.er(n, CFG1["d"], s))) for s in range(100, 200)]
+    assert abs(np.mean(ts) - mean) < 4 * math.sqrt(var / len(ts))
+    assert 0.5 * var < np.var(ts) < 2.0 * var
+
+
+# ------------------------------------------------ Triangle p-1-Reduction
+
+def test_tr_p0_is_identity(cfg1):
+    ro, col, st = O.triangle_reduce(cfg1, 0.0, 3)
+    assert st["selected"] == 0 and st["deleted"] == 0
+    assert np.array_equal(ro, cfg1.row_off) and np.array_equal(col, cfg1.col)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_tr_p1_output_triangle_free(cfg1, seed):
+    """p = 1 reduces every input triangle, so none survives; the output has
+    no triangle at all because it is a subgraph of the input."""
+    ro, col, st = O.triangle_reduce(cfg1, 1.0, seed)
+    assert st["selected"] == st["T"]
+    assert trace_triangles(ro, col, cfg1.n) == 0
+
+
+def test_k3_p1_deletes_exactly_one_edge():
+    g = gg.complete(3)
+    hits = np.zeros(3, dtype=np.int64)
+    edges = [(0, 1), (0, 2), (1, 2)]
+    for seed in range(3000):
+        ro, col, st = O.triangle_reduce(g, 1.0, seed)
+        assert st["T"] == 1 and st["selected"] == 1 and st["deleted"] == 1 and st["m_out"] == 2
+        missing = set(edges) - undirected(ro, col)
+        assert len(missing) == 1
+        hits[edges.index(missing.pop())] += 1
+    # rand(triangle) is uniform over the three edges: chi-square, 2 dof
+    chi2 = float(np.sum((hits - 1000.0) ** 2 / 1000.0))
+    assert chi2 < 13.8  # p = 0.001
+
+
+@pytest.mark.parametrize("p", [0.2, 0.5, 0.8])
+def test_tr_invariants(cfg1, p):
+    ro, col, st = O.triangle_reduce(cfg1, p, 11)
+    assert is_valid_csr(cfg1.n, ro, col)  # symmetric, sorted, same n
+    e_in = undirected(cfg1.row_off, cfg1.col)
+    e_out = undirected(ro, col)
+    d = e_in - e_out
+    assert e_out <= e_in
+    assert len(d) == st["deleted"] <= st["selected"] <= st["T"]
+    assert st["m_out"] == st["m_in"] - st["deleted"] == len(e_out)
+    in_tri = set()
+    for a, b, c in O.list_triangles(cfg1):
+        in_tri |= {(int(a), int(b)), (int(a), int(c)), (int(b), int(c))}
+    assert d <= in_tri  # every deleted edge lies in some input triangle
+
+
+def test_tr_selected_is_binomial(cfg1):
+    """Each triangle is selected independently with probability p."""
+    for p in (0.1, 0.5, 0.9):
+        zs = []
+        for seed in range(20):
+            _, _, st = O.triangle_reduce(cfg1, p, 1000 + seed)
+            t = st["T"]
+            zs.append((st["selected"] - p * t) / math.sqrt(t * p * (1 - p)))
+        z = np.sum(zs) / math.sqrt(len(zs))
+        assert abs(z) < 4.0, (p, z)
+
+
+def test_tr_expected_deletions_exact():
+    """E[|D|] = sum_e 1 - (1 - p/3)^{t_e}; t_e from dense A^2 (numpy)."""
+    g = gg.er(300, 60.0, 5)  # ~ 9k triangles, overlapping heavily
+    a = dense(g).astype(np.float64)
+    te = (a @ a)[np.triu_indices(g.n, 1)][a[np.triu_indices(g.n, 1)] > 0]
+    for p in (0.3, 0.7):
+        expect = float(np.sum(1.0 - (1.0 - p / 3.0) ** te))
+        var_ub = float(np.sum((1.0 - p / 3.0) ** te * (1.0 - (1.0 - p / 3.0) ** te)))
+        ds = [O.triangle_reduce(g, p, s)[2]["deleted"] for s in range(40)]
+        # deletions of different edges are not independent; allow a wide band
+        assert abs(np.mean(ds) - expect) < 6 * math.sqrt(3 * var_ub / len(ds)) + 1, (p, expect)
+        # "m - pT" (Table `tab:theory-schemes`) only bounds it: |D| <= pT on average
+        t = O.triangle_reduce(g, p, 0)[2]["T"]
+        assert expect <= p * t
+
+
+def test_tr_edge_disjoint_triangles_m_minus_pT():
+    """With edge-disjoint triangles E[|D|] = pT exactly (the m - pT entry)."""
+    g = gg.friendship(400)
+    p = 0.5
+    ds = [O.triangle_reduce(g, p, s)[2]["deleted"] for s in range(50)]
+    mean = np.mean(ds)
+    assert abs(mean - p * 400) < 4 * math.sqrt(400 * p * (1 - p) / 50)
+
+
+def test_tr_direction_matches_table_tcv(cfg1):
+    """Table `tab:tcv`: 0.9-1-TR keeps fewer triangles than 0.2-1-TR on every
+    graph; the oracle must show the same direction (p = reduction prob.)."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "tcv_triangles_per_vertex.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert all(float(r[3]) < float(r[2]) < float(r[1]) for r in rows)
+    g = gg.er(400, 40.0, 3)
+    t_after = {}
+    for p in (0.2, 0.9):
+        ro, col, _ = O.triangle_reduce(g, p, 9)
+        t_after[p] = trace_triangles(ro, col, g.n)
+    assert t_after[0.9] < t_after[0.2] < len(O.list_triangles(g))
+
+
+# ----------------------------------------------------- uniform sampling
+
+def test_es_direction_matches_table_tcv():
+    """Table `tab:tcv`: uniform sampling at p keeps a (1-p)^3 share of the
+    triangles (e.g. s-you 11.38 * 0.2^3 = 0.091).  The table is reproduced
+    to within its own noise, and the oracle's ratio on a triangle-rich graph
+    matches the table's ratio for each p."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "tcv_triangles_per_vertex.txt"))
+            if l.strip() and not l.startswith("#")]
+    cols = {0.8: 4, 0.5: 5, 0.2: 6}
+    g = gg.er(300, 90.0, 4)
+    t0 = trace_triangles(g.row_off, g.col, g.n)
+    for p, ci in cols.items():
+        table_ratio = float(np.median([float(r[ci]) / float(r[1]) for r in rows]))
+        assert abs(table_ratio - (1 - p) ** 3) < 0.05 * (1 - p) ** 3
+        ratios = []
+        for s in range(4):
+            ro, col, _ = O.edge_sample(g, p, 50 + s)
+            ratios.append(trace_triangles(ro, col, g.n) / t0)
+        assert abs(np.mean(ratios) - table_ratio) < 0.1 * table_ratio, (p, ratios, table_ratio)
+
+
+def test_es_deleted_is_binomial(cfg1):
+    m = cfg1.m
+    for p in (0.1, 0.5, 0.9):
+        zs = []
+        for seed in range(10):
+            ro, col, st = O.edge_sample(cfg1, p, seed)
+            assert st["m_out"] == m - st["deleted"] == len(col) // 2
+            zs.append((st["deleted"] - p * m) / math.sqrt(m * p * (1 - p)))
+        assert abs(np.sum(zs) / math.sqrt(len(zs))) < 4.0
+
+
+def test_es_symmetric_and_endpoints(cfg1):
+    ro, col, st = O.edge_sample(cfg1, 0.5, 3)
+    assert is_valid_csr(cfg1.n, ro, col)
+    ro0, col0, _ = O.edge_sample(cfg1, 0.0, 3)
+    assert np.array_equal(ro0, cfg1.row_off) and np.array_equal(col0, cfg1.col)
+    ro1, col1, st1 = O.edge_sample(cfg1, 1.0, 3)
+    assert len(col1) == 0 and st1["deleted"] == cfg1.m and np.all(ro1 == 0)
+
+
+# ------------------------------------------------- local per-row oracle
+
+@pytest.mark.parametrize("p,seed", [(0.5, 1), (0.2, 2), (1.0, 3)])
+def test_tr_rows_match_definition_on_every_row(p, seed):
+    """The per-row oracle (per-edge merge of full rows) gives the same rows
+    as the whole-graph oracle (forward listing)."""
+    g = gg.rmat(10, 8, 3)
+    ro, col, _ = O.triangle_reduce(g, p, seed)
+    rows = np.arange(g.n, dtype=np.uint32)
+    got = O.tr_rows(g, p, seed, rows)
+    for r in range(g.n):
+        assert np.array_equal(got[r], col[ro[r]:ro[r + 1]]), r
+
+
+def test_edge_triangle_counts_sum(cfg1):
+    t = O.edge_triangle_counts(cfg1)
+    assert int(t.sum()) == 6 * len(O.list_triangles(cfg1))
+    a = dense(cfg1)
+    a2 = a @ a
+    rows = np.repeat(np.arange(cfg1.n), np.diff(cfg1.row_off))
+    assert np.array_equal(t, a2[rows, cfg1.col.astype(np.int64)])
+
+
+def test_oracle_rejects_bad_p(cfg1):
+    for bad in (-0.01, 1.01, float("nan")):
+        with pytest.raises(ValueError):
+            O.triangle_reduce(cfg1, bad, 1)
+        with pytest.raises(ValueError):
+            O.edge_sample(cfg1, bad, 1)
+
+
+def test_determinism(cfg1):
+    a = O.triangle_reduce(cfg1, 0.5, 42)
+    b = O.triangle_reduce(cfg1, 0.5, 42)
+    c = O.triangle_reduce(cfg1, 0.5, 43)
+    assert np.array_equal(a[1], b[1]) and a[2] == b[2]
+    assert not np.array_equal(a[1], c[1])
