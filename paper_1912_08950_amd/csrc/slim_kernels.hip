@@ -1,0 +1,588 @@
+// HIP kernels of libslim (gfx950): degree-rank relabelling, DAG orientation,
+// triangle listing with selection and deletion marks, and CSR compaction.
+//
+// Data layout (all in HBM, caller-provided workspace):
+//   rank[n], order[n]   old id -> rank id and back; rank order = (degree, id)
+//   dag_col[m]          rank ids of the higher-ranked neighbours, rows laid
+//                       out in old-id row order (a stream compaction of CSR)
+//   dag_rng[n]          (begin, end) of row x of the DAG, indexed by rank id
+//   eid[nnz]            for every CSR entry, the DAG position of its edge
+//   del[m/32]           deletion bitmap over DAG positions
+#include "slim_internal.h"
+
+namespace slim {
+
+// ------------------------------------------------------------------ fills
+__global__ void k_fill_u32(uint32_t* p, uint64_t len, uint32_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < len;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_i64(int64_t* p, uint64_t len, int64_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < len;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+static unsigned grid_for(uint64_t len, unsigned cap = 65536) {
+  uint64_t b = (len + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  return (unsigned)(b < cap ? b : cap);
+}
+
+void fill_u32(uint32_t* p, uint64_t len, uint32_t v, hipStream_t s) {
+  if (len) hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(len)), dim3(kBlock), 0, s, p, len, v);
+}
+
+void fill_i64(int64_t* p, uint64_t len, int64_t v, hipStream_t s) {
+  if (len) hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(len)), dim3(kBlock), 0, s, p, len, v);
+}
+
+// ------------------------------------------------------------------- scan
+// Exclusive prefix sum of TI[len] into uint64[len+1] (out[len] = total):
+// per-block reduce, recursive scan of the block sums, per-block apply.
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ __forceinline__ uint64_t block_excl_sum64(uint64_t v, uint64_t* total,
+                                                     uint64_t* lds /*[kWavesPerBlock]*/) {
+  const int w = threadIdx.x / kWave;
+  uint64_t incl = wave_incl_sum64(v);
+  if (lane_id() == kWave - 1) lds[w] = incl;
+  __syncthreads();
+  uint64_t before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < kWavesPerBlock; ++i) {
+    if (i < w) before += lds[i];
+    all += lds[i];
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - v;
+}
+
+template <typename TI>
+__global__ void k_scan_reduce(const TI* in, uint64_t len, uint64_t* bsum) {
+  __shared__ uint64_t lds[kWavesPerBlock];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    uint64_t i = base + (uint64_t)k * kBlock + threadIdx.x;
+    if (i < len) s += (uint64_t)in[i];
+  }
+  uint64_t total;
+  block_excl_sum64(s, &total, lds);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+template <typename TI>
+__global__ void k_scan_apply(const TI* in, uint64_t len, const uint64_t* bbase, uint64_t* out) {
+  __shared__ uint64_t lds[kWavesPerBlock];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+  uint64_t v[kScanItems];
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    uint64_t i = base + k;
+    v[k] = i < len ? (uint64_t)in[i] : 0;
+    s += v[k];
+  }
+  uint64_t total;
+  uint64_t run = block_excl_sum64(s, &total, lds) + (bbase ? bbase[blockIdx.x] : 0);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    uint64_t i = base + k;
+    if (i < len) out[i] = run;
+    run += v[k];
+    if (i + 1 == len) out[len] = run;
+  }
+}
+
+static uint64_t scan_blocks(uint64_t len) { return (len + kScanTile - 1) / kScanTile; }
+
+uint64_t scan_tmp_elems(uint64_t len) {
+  uint64_t nb = scan_blocks(len);
+  if (nb <= 1) return 0;
+  return 2 * nb + 2 + scan_tmp_elems(nb);
+}
+
+template <typename TI>
+void scan_excl(const TI* in, uint64_t len, uint64_t* out, uint64_t* tmp, hipStream_t s) {
+  if (len == 0) {
+    fill_i64(reinterpret_cast<int64_t*>(out), 1, 0, s);
+    return;
+  }
+  uint64_t nb = scan_blocks(len);
+  if (nb == 1) {
+    hipLaunchKernelGGL(k_scan_apply<TI>, dim3(1), dim3(kBlock), 0, s, in, len,
+                       (const uint64_t*)nullptr, out);
+    return;
+  }
+  uint64_t* bsum = tmp;
+  uint64_t* bbase = tmp + nb + 1;
+  hipLaunchKernelGGL(k_scan_reduce<TI>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, len, bsum);
+  scan_excl<uint64_t>(bsum, nb, bbase, tmp + 2 * nb + 2, s);
+  hipLaunchKernelGGL(k_scan_apply<TI>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, len,
+                     (const uint64_t*)bbase, out);
+}
+
+template void scan_excl<uint32_t>(const uint32_t*, uint64_t, uint64_t*, uint64_t*, hipStream_t);
+template void scan_excl<uint64_t>(const uint64_t*, uint64_t, uint64_t*, uint64_t*, hipStream_t);
+
+// ------------------------------------------------------ stable radix sort
+// LSD radix sort of (uint32 key, uint32 value) pairs, 8-bit digits.  The
+// scatter ranks equal digits inside a wave with ballots, so the order of
+// equal keys is kept (stable).
+constexpr int kSortTile = kTile;
+
+__global__ void k_radix_hist(const uint32_t* keys, uint64_t n, int shift, uint32_t nb,
+                             uint32_t* hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+  for (int k = 0; k < kItems; ++k) {
+    uint64_t i = base + (uint64_t)k * kBlock + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void k_radix_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
+                                uint32_t* vout, uint64_t n, int shift, uint32_t nb,
+                                const uint64_t* off) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[kWavesPerBlock][256];
+  const int t = threadIdx.x, w = t / kWave;
+  base[t] = (uint32_t)off[(uint64_t)t * nb + blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kWavesPerBlock; ++i) wcnt[i][t] = 0;
+  __syncthreads();
+  const uint64_t tile0 = (uint64_t)blockIdx.x * kSortTile;
+  const uint64_t lt = lanemask_lt();
+  for (int k = 0; k < kItems; ++k) {
+    const uint64_t i = tile0 + (uint64_t)k * kBlock + t;
+    const bool valid = i < n;
+    uint32_t key = 0, val = 0;
+    if (valid) {
+      key = kin[i];
+      val = vin[i];
+    }
+    const uint32_t d = (key >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(valid && bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t rnk = __popcll(peers & lt);
+    if (valid && rnk == 0) wcnt[w][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = base[d] + rnk;
+      for (int i2 = 0; i2 < w; ++i2) pos += wcnt[i2][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int i2 = 0; i2 < kWavesPerBlock; ++i2) {
+      add += wcnt[i2][t];
+      wcnt[i2][t] = 0;
+    }
+    base[t] += add;
+    __syncthreads();
+  }
+}
+
+uint64_t sort_hist_elems(uint64_t n) {
+  uint64_t nb = (n + kSortTile - 1) / kSortTile;
+  return 256 * nb;
+}
+
+// Sorts (keys,vals) in buffers A by key with `passes` 8-bit passes, using B
+// as the ping-pong buffer.  Returns true if the result ended in B.
+bool radix_sort_pairs(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, uint64_t n,
+                      int passes, uint32_t* hist, uint64_t* hist_scan, uint64_t* scan_tmp,
+                      hipStream_t s) {
+  const uint32_t nb = (uint32_t)((n + kSortTile - 1) / kSortTile);
+  bool in_b = false;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    uint32_t* ki = in_b ? kb : ka;
+    uint32_t* vi = in_b ? vb : va;
+    uint32_t* ko = in_b ? ka : kb;
+    uint32_t* vo = in_b ? va : vb;
+    hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kBlock), 0, s, ki, n, shift, nb, hist);
+    scan_excl<uint32_t>(hist, (uint64_t)256 * nb, hist_scan, scan_tmp, s);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kBlock), 0, s, ki, vi, ko, vo, n, shift,
+                       nb, hist_scan);
+    in_b = !in_b;
+  }
+  return in_b;
+}
+
+// ------------------------------------------------------- degree ranking
+__global__ void k_deg_keys(const int64_t* row_off, uint64_t n, uint32_t* key, uint32_t* val) {
+  for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
+       v += (uint64_t)gridDim.x * blockDim.x) {
+    key[v] = (uint32_t)(row_off[v + 1] - row_off[v]);
+    val[v] = (uint32_t)v;
+  }
+}
+
+__global__ void k_invert(const uint32_t* order, uint64_t n, uint32_t* rank) {
+  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
+       x += (uint64_t)gridDim.x * blockDim.x)
+    rank[order[x]] = (uint32_t)x;
+}
+
+void degree_rank(const int64_t* row_off, uint64_t n, int passes, uint32_t* ka, uint32_t* va,
+                 uint32_t* kb, uint32_t* vb, uint32_t* hist, uint64_t* hist_scan,
+                 uint64_t* scan_tmp, uint32_t** order_out, uint32_t* rank, hipStream_t s) {
+  hipLaunchKernelGGL(k_deg_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, row_off, n, ka, va);
+  bool in_b = radix_sort_pairs(ka, va, kb, vb, n, passes, hist, hist_scan, scan_tmp, s);
+  uint32_t* order = in_b ? vb : va;
+  hipLaunchKernelGGL(k_invert, dim3(grid_for(n)), dim3(kBlock), 0, s, order, n, rank);
+  *order_out = order;
+}
+
+// ------------------------------------------------------ CSR tile machinery
+// Tile t holds CSR entries [t*kTile, (t+1)*kTile).  tile_lo[t] is the first
+// row whose start offset is >= t*kTile, so tile t "owns" the row starts of
+// rows [tile_lo[t], tile_lo[t+1]).
+__global__ void k_tile_lo(const int64_t* row_off, uint64_t n, uint64_t nnz, uint64_t ntiles,
+                          uint32_t* tile_lo) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t <= ntiles;
+       t += (uint64_t)gridDim.x * blockDim.x) {
+    int64_t j = (int64_t)(t * kTile);
+    if ((uint64_t)j > nnz) j = (int64_t)nnz;
+    uint64_t lo = 0, hi = n;  // first r in [0,n] with row_off[r] >= j
+    while (lo < hi) {
+      uint64_t mid = (lo + hi) >> 1;
+      if (row_off[mid] < j)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    tile_lo[t] = (uint32_t)lo;
+  }
+}
+
+struct TileRows {
+  uint32_t srow[kTile];
+  uint32_t cmax[kChunks];
+};
+
+// Fills L.srow so that the row of tile entry i is max(srow[i], cmax[i/64]).
+__device__ void tile_rows(const int64_t* row_off, int64_t j0, uint32_t lo, uint32_t hi,
+                          TileRows& L) {
+  const int t = threadIdx.x, w = t / kWave, lane = lane_id();
+  for (int i = t; i < kTile; i += kBlock) L.srow[i] = 0;
+  __syncthreads();
+  if (t == 0) L.srow[0] = lo > 0 ? lo - 1 : 0;
+  __syncthreads();
+  for (uint32_t r = lo + t; r < hi; r += kBlock) {
+    const int64_t b = row_off[r], e = row_off[r + 1];
+    const int64_t s = b - j0;
+    if (e > b && s >= 0 && s < kTile) L.srow[s] = r;
+  }
+  __syncthreads();
+  for (int c = w; c < kChunks; c += kWavesPerBlock) {
+    uint32_t v = wave_incl_max(L.srow[c * kWave + lane]);
+    L.srow[c * kWave + lane] = v;
+    if (lane == kWave - 1) L.cmax[c] = v;
+  }
+  __syncthreads();
+  if (w == 0) {
+    const uint32_t v = L.cmax[lane];
+    const uint32_t incl = wave_incl_max(v);
+    uint32_t excl = __shfl_up(incl, 1, kWave);
+    if (lane == 0) excl = 0;
+    L.cmax[lane] = excl;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t tile_row_of(const TileRows& L, int i) {
+  const uint32_t a = L.srow[i], b = L.cmax[i >> 6];
+  return a > b ? a : b;
+}
+
+// ------------------------------------------------ flag stream compaction
+// Policies decide per CSR entry j (row r) whether it is kept and what is
+// written; kept entries keep their CSR order, so rows stay sorted.
+struct OrientPolicy {  // keep (r,c) iff rank(c) > rank(r); write rank(c)
+  static constexpr bool kNeedRows = true;
+  const uint32_t* col;
+  const uint32_t* rank;
+  uint32_t* eid;  // eid[j] = DAG position of the kept entry
+  __device__ bool flag(uint64_t j, uint32_t r) const { return rank[col[j]] > rank[r]; }
+  __device__ uint32_t value(uint64_t j) const { return rank[col[j]]; }
+  __device__ void kept(uint64_t j, uint64_t pos) const { eid[j] = (uint32_t)pos; }
+};
+
+struct KeepPolicy {  // TR output: keep (r,c) iff its edge is not marked deleted
+  static constexpr bool kNeedRows = false;
+  const uint32_t* col;
+  const uint32_t* eid;
+  const uint32_t* del;
+  uint64_t m;
+  __device__ bool flag(uint64_t j, uint32_t) const {
+    const uint32_t e = eid[j];
+    return e >= m || !bit_get(del, e);  // e >= m only for inputs breaking the contract
+  }
+  __device__ uint32_t value(uint64_t j) const { return col[j]; }
+  __device__ void kept(uint64_t, uint64_t) const {}
+};
+
+struct SamplePolicy {  // ES output: keep {a<b} iff Philox(a,b,0,1).w0 >= thr
+  static constexpr bool kNeedRows = true;
+  const uint32_t* col;
+  uint64_t thr;
+  uint32_t k0, k1;
+  __device__ bool flag(uint64_t j, uint32_t r) const {
+    const uint32_t c = col[j];
+    const uint32_t a = c < r ? c : r, b = c < r ? r : c;
+    uint32_t w0, w1;
+    philox_w01(a, b, 0u, 1u, k0, k1, w0, w1);
+    return !((uint64_t)w0 < thr);
+  }
+  __device__ uint32_t value(uint64_t j) const { return col[j]; }
+  __device__ void kept(uint64_t, uint64_t) const {}
+};
+
+template <class P>
+__global__ __launch_bounds__(kBlock) void k_compact_count(P p, const int64_t* row_off,
+                                                          const uint32_t* tile_lo, uint64_t nnz,
+                                                          uint32_t* tile_cnt) {
+  __shared__ TileRows L;
+  __shared__ uint32_t wsum[kWavesPerBlock];
+  const uint64_t t = blockIdx.x;
+  const int64_t j0 = (int64_t)(t * kTile);
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  if (P::kNeedRows) tile_rows(row_off, j0, tile_lo[t], tile_lo[t + 1], L);
+  uint32_t cnt = 0;
+  for (int c = w; c < kChunks; c += kWavesPerBlock) {
+    const int i = c * kWave + lane;
+    const uint64_t j = (uint64_t)j0 + i;
+    bool f = false;
+    if (j < nnz) f = p.flag(j, P::kNeedRows ? tile_row_of(L, i) : 0u);
+    cnt += __popcll(__ballot(f));
+  }
+  if (lane == 0) wsum[w] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int i = 0; i < kWavesPerBlock; ++i) s += wsum[i];
+    tile_cnt[t] = s;
+  }
+}
+
+template <class P, typename OffT>
+__global__ __launch_bounds__(kBlock) void k_compact_scatter(
+    P p, const int64_t* row_off, const uint32_t* tile_lo, uint64_t n, uint64_t nnz,
+    uint64_t ntiles, const uint64_t* tile_base, uint32_t* out, uint64_t out_cap,
+    OffT* row_start) {
+  __shared__ TileRows L;
+  __shared__ uint64_t cmask[kChunks];
+  __shared__ uint32_t cbase[kChunks];
+  const uint64_t t = blockIdx.x;
+  const int64_t j0 = (int64_t)(t * kTile);
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const uint32_t lo = tile_lo[t], hi = tile_lo[t + 1];
+  if (P::kNeedRows) tile_rows(row_off, j0, lo, hi, L);
+  uint32_t fbits = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int c = w + k * kWavesPerBlock;
+    const int i = c * kWave + lane;
+    const uint64_t j = (uint64_t)j0 + i;
+    bool f = false;
+    if (j < nnz) f = p.flag(j, P::kNeedRows ? tile_row_of(L, i) : 0u);
+    const uint64_t m = __ballot(f);
+    if (lane == 0) cmask[c] = m;
+    if (f) fbits |= 1u << k;
+  }
+  __syncthreads();
+  if (w == 0) {
+    const uint32_t v = __popcll(cmask[lane]);
+    const uint64_t incl = wave_incl_sum64(v);
+    cbase[lane] = (uint32_t)(incl - v);
+  }
+  __syncthreads();
+  const uint64_t base = tile_base[t];
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    if (fbits & (1u << k)) {
+      const int c = w + k * kWavesPerBlock;
+      const uint64_t j = (uint64_t)j0 + c * kWave + lane;
+      const uint64_t pos = base + cbase[c] + __popcll(cmask[c] & lt);
+      if (pos < out_cap) {  // always true for inputs that meet the CSR contract
+        out[pos] = p.value(j);
+        p.kept(j, pos);
+      }
+    }
+  }
+  for (uint32_t r = lo + threadIdx.x; r < hi; r += kBlock) {
+    const int64_t s = row_off[r] - j0;
+    const int c = (int)(s >> 6);
+    const uint64_t below = (uint64_t(1) << (s & 63)) - 1;
+    const uint64_t v = base + cbase[c] + __popcll(cmask[c] & below);
+    row_start[r] = (OffT)(v < out_cap ? v : out_cap);
+  }
+  if (t + 1 == ntiles) {
+    uint64_t total = base + cbase[kChunks - 1] + __popcll(cmask[kChunks - 1]);
+    if (total > out_cap) total = out_cap;
+    for (uint64_t r = hi + threadIdx.x; r <= n; r += kBlock) row_start[r] = (OffT)total;
+  }
+}
+
+template <class P, typename OffT>
+void compact(const P& p, const int64_t* row_off, const uint32_t* tile_lo, uint64_t n,
+             uint64_t nnz, uint64_t ntiles, uint32_t* tile_cnt, uint64_t* tile_base,
+             uint64_t* scan_tmp, uint32_t* out, uint64_t out_cap, OffT* row_start,
+             hipStream_t s) {
+  hipLaunchKernelGGL(k_compact_count<P>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, p, row_off,
+                     tile_lo, nnz, tile_cnt);
+  scan_excl<uint32_t>(tile_cnt, ntiles, tile_base, scan_tmp, s);
+  hipLaunchKernelGGL((k_compact_scatter<P, OffT>), dim3((unsigned)ntiles), dim3(kBlock), 0, s, p,
+                     row_off, tile_lo, n, nnz, ntiles, (const uint64_t*)tile_base, out, out_cap,
+                     row_start);
+}
+
+void tile_lo_build(const int64_t* row_off, uint64_t n, uint64_t nnz, uint64_t ntiles,
+                   uint32_t* tile_lo, hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_lo, dim3(grid_for(ntiles + 1)), dim3(kBlock), 0, s, row_off, n, nnz,
+                     ntiles, tile_lo);
+}
+
+// DAG: dag_col = rank ids of forward entries; eid for forward entries.
+void orient(const int64_t* row_off, const uint32_t* col, const uint32_t* rank, uint64_t n,
+            uint64_t nnz, uint64_t ntiles, const uint32_t* tile_lo, uint32_t* tile_cnt,
+            uint64_t* tile_base, uint64_t* scan_tmp, uint32_t* dag_col, uint32_t* eid,
+            uint32_t* fstart, hipStream_t s) {
+  OrientPolicy p{col, rank, eid};
+  compact<OrientPolicy, uint32_t>(p, row_off, tile_lo, n, nnz, ntiles, tile_cnt, tile_base,
+                                  scan_tmp, dag_col, nnz / 2, fstart, s);
+}
+
+__global__ void k_dag_rng(const uint32_t* order, const uint32_t* fstart, uint64_t n,
+                          uint2* dag_rng) {
+  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
+       x += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t u = order[x];
+    dag_rng[x] = make_uint2(fstart[u], fstart[u + 1]);
+  }
+}
+
+void dag_ranges(const uint32_t* order, const uint32_t* fstart, uint64_t n, uint2* dag_rng,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_dag_rng, dim3(grid_for(n)), dim3(kBlock), 0, s, order, fstart, n,
+                     dag_rng);
+}
+
+void compact_tr(const int64_t* row_off, const uint32_t* col, const uint32_t* eid,
+                const uint32_t* del, uint64_t n, uint64_t nnz, uint64_t ntiles,
+                const uint32_t* tile_lo, uint32_t* tile_cnt, uint64_t* tile_base,
+                uint64_t* scan_tmp, uint32_t* out_col, int64_t* out_row_off, hipStream_t s) {
+  KeepPolicy p{col, eid, del, nnz / 2};
+  compact<KeepPolicy, int64_t>(p, row_off, tile_lo, n, nnz, ntiles, tile_cnt, tile_base,
+                               scan_tmp, out_col, nnz, out_row_off, s);
+}
+
+void compact_es(const int64_t* row_off, const uint32_t* col, uint64_t thr, uint64_t seed,
+                uint64_t n, uint64_t nnz, uint64_t ntiles, const uint32_t* tile_lo,
+                uint32_t* tile_cnt, uint64_t* tile_base, uint64_t* scan_tmp, uint32_t* out_col,
+                int64_t* out_row_off, hipStream_t s) {
+  SamplePolicy p{col, thr, (uint32_t)seed, (uint32_t)(seed >> 32)};
+  compact<SamplePolicy, int64_t>(p, row_off, tile_lo, n, nnz, ntiles, tile_cnt, tile_base,
+                                 scan_tmp, out_col, nnz, out_row_off, s);
+}
+
+// --------------------------------------------------------------- stats
+__global__ void k_stats(uint64_t n, uint64_t nnz, const uint64_t* counters,
+                        const uint64_t* kept, slim_stats_t* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const uint64_t m = nnz / 2, m_out = (kept ? *kept : nnz) / 2;
+    st->n = n;
+    st->m_in = m;
+    st->triangles = counters ? counters[0] : 0;
+    st->selected = counters ? counters[1] : 0;
+    st->deleted = m - m_out;
+    st->m_out = m_out;
+  }
+}
+
+void write_stats(uint64_t n, uint64_t nnz, const uint64_t* counters, const uint64_t* kept,
+                 slim_stats_t* st, hipStream_t s) {
+  if (st) hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, s, n, nnz, counters, kept, st);
+}
+
+// ------------------------------------------------------------ validation
+// err bits: 1 offsets, 2 id >= n, 4 self-loop, 8 unsorted/duplicate, 16 asymmetric
+__global__ void k_validate_offsets(const int64_t* row_off, uint64_t n, uint64_t nnz,
+                                   uint32_t* err) {
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r <= n;
+       r += (uint64_t)gridDim.x * blockDim.x) {
+    bool bad = false;
+    if (r == 0 && row_off[0] != 0) bad = true;
+    if (r == n && row_off[n] != (int64_t)nnz) bad = true;
+    if (r < n && row_off[r + 1] < row_off[r]) bad = true;
+    if (bad) atomicOr(err, 1u);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_validate_entries(const int64_t* row_off,
+                                                             const uint32_t* col, uint64_t n,
+                                                             uint64_t nnz,
+                                                             const uint32_t* tile_lo,
+                                                             uint32_t* err) {
+  __shared__ TileRows L;
+  const uint64_t t = blockIdx.x;
+  const int64_t j0 = (int64_t)(t * kTile);
+  tile_rows(row_off, j0, tile_lo[t], tile_lo[t + 1], L);
+  uint32_t e = 0;
+  for (int i = threadIdx.x; i < kTile; i += kBlock) {
+    const uint64_t j = (uint64_t)j0 + i;
+    if (j >= nnz) break;
+    const uint32_t r = tile_row_of(L, i);
+    const uint32_t c = col[j];
+    if ((uint64_t)c >= n) {
+      e |= 2u;
+      continue;
+    }
+    if (c == r) e |= 4u;
+    if ((int64_t)j > row_off[r] && col[j - 1] >= c) e |= 8u;
+    int64_t lo = row_off[c], hi = row_off[c + 1];
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (col[mid] < r)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    if (!(lo < row_off[c + 1] && col[lo] == r)) e |= 16u;
+  }
+  if (e) atomicOr(err, e);
+}
+
+void validate_offsets(const int64_t* row_off, uint64_t n, uint64_t nnz, uint32_t* err,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_validate_offsets, dim3(grid_for(n + 1)), dim3(kBlock), 0, s, row_off, n,
+                     nnz, err);
+}
+
+void validate_entries(const int64_t* row_off, const uint32_t* col, uint64_t n, uint64_t nnz,
+                      uint64_t ntiles, const uint32_t* tile_lo, uint32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate_entries, dim3((unsigned)ntiles), dim3(kBlock), 0, s, row_off,
+                     col, n, nnz, tile_lo, err);
+}
+
+}  // namespace slim

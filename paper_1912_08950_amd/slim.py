@@ -1,0 +1,216 @@
+"""ctypes binding of libslim.so (include/slim.h).
+
+Argument marshalling only: every step of Triangle p-1-Reduction and edge
+sampling runs in the library's HIP kernels.  PyTorch provides device memory
+(tensors) and the stream.  There is no CPU fallback: if libslim.so is not
+built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libslim.so")
+
+OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, EAGAIN = 0, -1, -2, -3, -4, -5
+VALIDATE = 1
+OP_TR, OP_ES = 1, 2
+STAT_KEYS = ("n", "m_in", "triangles", "selected", "deleted", "m_out")
+
+# Exported symbols of libslim.so, in include/slim.h order.
+SYMBOLS = ("slim_last_error", "slim_strerror", "slim_version", "slim_load_csr",
+           "slim_graph_free", "slim_workspace_size", "slim_triangle_reduce", "slim_edge_sample",
+           "slim_tune_set", "slim_tune_get", "slim_profile_enable", "slim_profile_read")
+
+
+class Phase(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("ms", ctypes.c_float)]
+
+
+class SlimError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} ({code})")
+        self.code = code
+
+
+def _bind(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, u64, u32, dbl, i32 = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double,
+                              ctypes.c_int)
+    lib.slim_last_error.restype = ctypes.c_char_p
+    lib.slim_last_error.argtypes = []
+    lib.slim_strerror.restype = ctypes.c_char_p
+    lib.slim_strerror.argtypes = [i32]
+    lib.slim_version.restype = i32
+    lib.slim_version.argtypes = []
+    lib.slim_load_csr.restype = i32
+    lib.slim_load_csr.argtypes = [vp, vp, u64, u64, u32, vp, ctypes.POINTER(vp)]
+    lib.slim_graph_free.restype = None
+    lib.slim_graph_free.argtypes = [vp]
+    lib.slim_workspace_size.restype = i32
+    lib.slim_workspace_size.argtypes = [vp, i32, ctypes.POINTER(u64)]
+    for fn in (lib.slim_triangle_reduce, lib.slim_edge_sample):
+        fn.restype = i32
+        fn.argtypes = [vp, dbl, u64, vp, u64, vp, vp, vp, vp]
+    lib.slim_tune_set.restype = i32
+    lib.slim_tune_set.argtypes = [ctypes.c_char_p, ctypes.c_int64]
+    lib.slim_tune_get.restype = i32
+    lib.slim_tune_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
+    lib.slim_profile_enable.restype = i32
+    lib.slim_profile_enable.argtypes = [i32]
+    lib.slim_profile_read.restype = i32
+    lib.slim_profile_read.argtypes = [ctypes.POINTER(Phase), i32, ctypes.POINTER(i32)]
+    return lib
+
+
+_lib = _bind()
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise SlimError(rc, _lib.slim_last_error().decode())
+
+
+def _stream_handle(stream, device) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return int(stream.cuda_stream)
+
+
+def version() -> int:
+    return int(_lib.slim_version())
+
+
+def tune_set(key: str, value: int):
+    """Set a scheduling knob (never changes results)."""
+    _check(_lib.slim_tune_set(key.encode(), int(value)))
+
+
+def tune_get(key: str) -> int:
+    v = ctypes.c_int64(0)
+    _check(_lib.slim_tune_get(key.encode(), ctypes.byref(v)))
+    return int(v.value)
+
+
+def profile_enable(on: bool = True):
+    """Bracket each phase of the following compute calls with HIP events."""
+    _check(_lib.slim_profile_enable(1 if on else 0))
+
+
+def profile_read() -> list[tuple[str, float]]:
+    """(phase, ms) of the most recent compute call (waits for its events)."""
+    arr = (Phase * 32)()
+    cnt = ctypes.c_int(0)
+    _check(_lib.slim_profile_read(arr, 32, ctypes.byref(cnt)))
+    return [(arr[i].name.decode(), float(arr[i].ms)) for i in range(min(cnt.value, 32))]
+
+
+class Graph:
+    """A device-resident CSR wrapped in a library handle.
+
+    ``row_off``: int64 tensor [n+1]; ``col``: int32/uint32 tensor [nnz] holding
+    uint32 vertex ids.  The tensors are kept alive by this object.
+    """
+
+    def __init__(self, row_off: torch.Tensor, col: torch.Tensor, validate: bool = False,
+                 stream=None):
+        if row_off.dtype != torch.int64 or not row_off.is_cuda or not row_off.is_contiguous():
+            raise ValueError("row_off must be a contiguous int64 CUDA tensor")
+        if col.element_size() != 4 or not col.is_cuda or not col.is_contiguous():
+            raise ValueError("col must be a contiguous 32-bit CUDA tensor")
+        self.row_off, self.col = row_off, col
+        self.device = row_off.device
+        self.n = int(row_off.numel() - 1)
+        self.nnz = int(col.numel())
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = _lib.slim_load_csr(row_off.data_ptr(), col.data_ptr() if self.nnz else None,
+                                    self.n, self.nnz, VALIDATE if validate else 0,
+                                    _stream_handle(stream, self.device), ctypes.byref(h))
+        _check(rc)
+        self._h = h
+
+    @classmethod
+    def from_numpy(cls, row_off: np.ndarray, col: np.ndarray, device="cuda:0",
+                   validate: bool = False) -> "Graph":
+        ro = torch.from_numpy(np.ascontiguousarray(row_off, dtype=np.int64)).to(device)
+        c = np.ascontiguousarray(col, dtype=np.uint32).view(np.int32)
+        ct = torch.from_numpy(c).to(device) if c.size else torch.zeros(1, dtype=torch.int32,
+                                                                     device=device)[:0]
+        return cls(ro, ct, validate=validate)
+
+    @classmethod
+    def from_csr(cls, g, device="cuda:0", validate: bool = False) -> "Graph":
+        return cls.from_numpy(g.row_off, g.col, device=device, validate=validate)
+
+    @property
+    def m(self) -> int:
+        return self.nnz // 2
+
+    def workspace_size(self, op: int) -> int:
+        b = ctypes.c_uint64(0)
+        _check(_lib.slim_workspace_size(self._h, op, ctypes.byref(b)))
+        return int(b.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.slim_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Buffers:
+    """Workspace and output tensors for one graph and one operation, reusable
+    across calls (the library itself allocates nothing)."""
+
+    def __init__(self, g: Graph, op: int):
+        self.g, self.op = g, op
+        dev = g.device
+        self.ws_bytes = g.workspace_size(op)
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
+        self.out_row_off = torch.empty(g.n + 1, dtype=torch.int64, device=dev)
+        self.out_col = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=dev)
+        self.stats = torch.zeros(len(STAT_KEYS), dtype=torch.int64, device=dev)
+
+
+def _run(fn, g: Graph, p: float, seed: int, bufs: Buffers | None, stream):
+    if bufs is None:
+        bufs = Buffers(g, OP_TR if fn is _lib.slim_triangle_reduce else OP_ES)
+    with torch.cuda.device(g.device):
+        rc = fn(g._h, float(p), int(seed) & (2**64 - 1), bufs.ws.data_ptr(), bufs.ws_bytes,
+                bufs.out_row_off.data_ptr(), bufs.out_col.data_ptr(), bufs.stats.data_ptr(),
+                _stream_handle(stream, g.device))
+    _check(rc)
+    return bufs
+
+
+def triangle_reduce(g: Graph, p: float, seed: int, bufs: Buffers | None = None, stream=None):
+    """Enqueue Triangle p-1-Reduction; returns the Buffers holding the output
+    CSR (out_row_off, out_col) and stats (valid after stream sync)."""
+    return _run(_lib.slim_triangle_reduce, g, p, seed, bufs, stream)
+
+
+def edge_sample(g: Graph, p: float, seed: int, bufs: Buffers | None = None, stream=None):
+    """Enqueue uniform edge sampling (p = deletion probability)."""
+    return _run(_lib.slim_edge_sample, g, p, seed, bufs, stream)
+
+
+def result_numpy(bufs: Buffers):
+    """Synchronise and copy a result to host: (row_off, col, stats dict)."""
+    torch.cuda.synchronize(bufs.g.device)
+    ro = bufs.out_row_off.cpu().numpy()
+    nnz_out = int(ro[-1])
+    col = bufs.out_col[:nnz_out].cpu().numpy().view(np.uint32)
+    st = dict(zip(STAT_KEYS, (int(x) for x in bufs.stats.cpu().numpy())))
+    return ro, col, st

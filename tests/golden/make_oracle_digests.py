@@ -1,0 +1,68 @@
+"""Write tests/golden/oracle_digests.json: SHA-256 digests of the CPU
+oracle's full outputs on the large synthetic workloads, so GPU tests can
+check bit-exact parity without rerunning a long single-threaded oracle.
+
+Calls only oracle/ (and the seeded input generator).  Usage:
+    python tests/golden/make_oracle_digests.py [case ...]
+Cases: rmat20_tr_p0.2 rmat20_tr_p0.5 rmat20_tr_p0.8 rmat20_es_p0.5
+       rmat24_tr_p0.5 rmat24_es_p0.5
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_digests.json")
+
+CASES = {
+    "rmat20_tr_p0.2": (20, "tr", 0.2),
+    "rmat20_tr_p0.5": (20, "tr", 0.5),
+    "rmat20_tr_p0.8": (20, "tr", 0.8),
+    "rmat20_es_p0.5": (20, "es", 0.5),
+    "rmat24_tr_p0.5": (24, "tr", 0.5),
+    "rmat24_es_p0.5": (24, "es", 0.5),
+}
+GEN_SEED, OP_SEED, EDGE_FACTOR = 1, 1, 16
+
+
+def csr_digest(row_off, col) -> str:
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(row_off, dtype="<i8").tobytes())
+    h.update(np.ascontiguousarray(col, dtype="<u4").tobytes())
+    return h.hexdigest()
+
+
+def main(names):
+    from oracle import oracle
+    from paper_1912_08950_amd import graphgen
+
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    graphs = {}
+    for name in names:
+        scale, op, p = CASES[name]
+        if scale not in graphs:
+            graphs = {scale: graphgen.rmat(scale, EDGE_FACTOR, GEN_SEED)}
+        g = graphs[scale]
+        t0 = time.time()
+        fn = oracle.triangle_reduce if op == "tr" else oracle.edge_sample
+        ro, col, st = fn(g, p, OP_SEED)
+        data[name] = {
+            "graph": f"rmat scale={scale} edge_factor={EDGE_FACTOR} seed={GEN_SEED}",
+            "graph_sha256": csr_digest(g.row_off, g.col),
+            "op": op, "p": p, "seed": OP_SEED,
+            "out_sha256": csr_digest(ro, col),
+            "stats": st,
+            "oracle_seconds": round(time.time() - t0, 1),
+        }
+        json.dump(data, open(OUT + ".tmp", "w"), indent=1, sort_keys=True)
+        os.replace(OUT + ".tmp", OUT)
+        print(name, data[name], flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or list(CASES))
