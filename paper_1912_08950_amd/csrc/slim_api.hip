@@ -67,6 +67,7 @@ struct Common {
 struct TrLayout : Common {
   uint64_t ka, va, kb, vb, rank, hist, hist_scan;
   uint64_t fstart, dag_rng, dag_col, eid, del, counters;
+  uint64_t sort_lists, sort_counts, tri_tlo, tri_ctr;
   uint64_t total;
   int passes;
 };
@@ -111,6 +112,10 @@ TrLayout tr_layout(uint64_t n, uint64_t nnz) {
   L.eid = c.take<uint32_t>(nnz);
   L.del = c.take<uint32_t>(ceil_div(m, 32) + 1);
   L.counters = c.take<uint64_t>(4);
+  L.sort_lists = c.take<uint32_t>(3 * n);
+  L.sort_counts = c.take<uint32_t>(4);
+  L.tri_tlo = c.take<uint32_t>(slim::tri_tiles(nnz) + 1);
+  L.tri_ctr = c.take<uint32_t>(4);
   L.total = c.off;
   return L;
 }
@@ -324,6 +329,11 @@ int slim_triangle_reduce(const slim_graph_t* g, double p, uint64_t seed, void* d
   slim::orient(g->row_off, g->col, rank, n, nnz, L.ntiles, tile_lo, tile_cnt, tile_base, scan_tmp,
                dag_col, eid, fstart, s);
   slim::dag_ranges(order, fstart, n, dag_rng, s);
+  slim::sort_rows(dag_rng, n, dag_col, at<uint32_t>(d_ws, L.sort_lists),
+                  at<uint32_t>(d_ws, L.sort_counts), g->num_cu, s);
+  uint32_t* tri_tlo = at<uint32_t>(d_ws, L.tri_tlo);
+  slim::tile_lo_build(g->row_off, n, nnz, slim::tri_tiles(nnz), tri_tlo, s,
+                      slim::tri_tile_entries());
   slim::fill_u32(del, ceil_div(nnz / 2, 32) + 1, 0, s);
   slim::fill_u32(reinterpret_cast<uint32_t*>(counters), 8, 0, s);
   prof_end(s);
@@ -333,16 +343,18 @@ int slim_triangle_reduce(const slim_graph_t* g, double p, uint64_t seed, void* d
   a.rank = rank;
   a.order = order;
   a.dag_rng = dag_rng;
+  a.fstart = fstart;
   a.dag_col = dag_col;
   a.eid = eid;
   a.del = del;
   a.counters = counters;
   a.n = n;
+  a.nnz = nnz;
   a.thr = threshold(p);
   a.k0 = (uint32_t)seed;
   a.k1 = (uint32_t)(seed >> 32);
   prof_begin("triangles", s);
-  slim::triangles(a, g->num_cu, s);
+  slim::triangles(a, tri_tlo, at<uint32_t>(d_ws, L.tri_ctr), g->num_cu, s);
   prof_end(s);
   prof_begin("compact", s);
   slim::compact_tr(g->row_off, g->col, eid, del, n, nnz, L.ntiles, tile_lo, tile_cnt, tile_base,

@@ -22,7 +22,7 @@ void degree_rank(const int64_t* row_off, uint64_t n, int passes, uint32_t* ka, u
                  uint64_t* scan_tmp, uint32_t** order_out, uint32_t* rank, hipStream_t s);
 
 void tile_lo_build(const int64_t* row_off, uint64_t n, uint64_t nnz, uint64_t ntiles,
-                   uint32_t* tile_lo, hipStream_t s);
+                   uint32_t* tile_lo, hipStream_t s, uint64_t tile = kTile);
 void orient(const int64_t* row_off, const uint32_t* col, const uint32_t* rank, uint64_t n,
             uint64_t nnz, uint64_t ntiles, const uint32_t* tile_lo, uint32_t* tile_cnt,
             uint64_t* tile_base, uint64_t* scan_tmp, uint32_t* dag_col, uint32_t* eid,
@@ -44,27 +44,38 @@ void validate_offsets(const int64_t* row_off, uint64_t n, uint64_t nnz, uint32_t
 void validate_entries(const int64_t* row_off, const uint32_t* col, uint64_t n, uint64_t nnz,
                       uint64_t ntiles, const uint32_t* tile_lo, uint32_t* err, hipStream_t s);
 
+// DAG rows longer than kSortMin are sorted by rank id (slim_sort.hip); the
+// triangle kernel scans shorter rows whole.
+constexpr uint32_t kSortMin = 32;
+void sort_rows(const uint2* dag_rng, uint64_t n, uint32_t* dag_col, uint32_t* lists,
+               uint32_t* counts, int num_cu, hipStream_t s);
+
 // Triangle listing + selection + deletion marks (slim_tri.hip).
 struct TriArgs {
   const int64_t* row_off;
   const uint32_t* col;
   const uint32_t* rank;
   const uint32_t* order;
-  const uint2* dag_rng;
+  const uint2* dag_rng;    // DAG row of each rank id
+  const uint32_t* fstart;  // DAG row start of each original id (n+1)
   const uint32_t* dag_col;
   uint32_t* eid;       // backward CSR entries get their DAG position here
   uint32_t* del;       // deletion bitmap over DAG positions
   uint64_t* counters;  // [0] triangles, [1] selected
   uint64_t n;
+  uint64_t nnz;
   uint64_t thr;
   uint32_t k0, k1;
 };
-void triangles(const TriArgs& a, int num_cu, hipStream_t s);
+uint64_t tri_tiles(uint64_t nnz);
+uint64_t tri_tile_entries();
+void triangles(const TriArgs& a, const uint32_t* tlo, uint32_t* tile_ctr, int num_cu,
+               hipStream_t s);
 
 // Scheduling knobs (slim_tune_set); never change results.
 struct Tuning {
   int tri_chunk = 2048;
-  int tri_blocks_per_cu = 12;
+  int tri_blocks_per_cu = 2;
 };
 Tuning& tuning();
 

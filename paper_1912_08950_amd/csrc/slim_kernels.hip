@@ -257,10 +257,10 @@ void degree_rank(const int64_t* row_off, uint64_t n, int passes, uint32_t* ka, u
 // row whose start offset is >= t*kTile, so tile t "owns" the row starts of
 // rows [tile_lo[t], tile_lo[t+1]).
 __global__ void k_tile_lo(const int64_t* row_off, uint64_t n, uint64_t nnz, uint64_t ntiles,
-                          uint32_t* tile_lo) {
+                          uint64_t tile, uint32_t* tile_lo) {
   for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t <= ntiles;
        t += (uint64_t)gridDim.x * blockDim.x) {
-    int64_t j = (int64_t)(t * kTile);
+    int64_t j = (int64_t)(t * tile);
     if ((uint64_t)j > nnz) j = (int64_t)nnz;
     uint64_t lo = 0, hi = n;  // first r in [0,n] with row_off[r] >= j
     while (lo < hi) {
@@ -321,10 +321,9 @@ struct OrientPolicy {  // keep (r,c) iff rank(c) > rank(r); write rank(c)
   static constexpr bool kNeedRows = true;
   const uint32_t* col;
   const uint32_t* rank;
-  uint32_t* eid;  // eid[j] = DAG position of the kept entry
   __device__ bool flag(uint64_t j, uint32_t r) const { return rank[col[j]] > rank[r]; }
   __device__ uint32_t value(uint64_t j) const { return rank[col[j]]; }
-  __device__ void kept(uint64_t j, uint64_t pos) const { eid[j] = (uint32_t)pos; }
+  __device__ void kept(uint64_t, uint64_t) const {}
 };
 
 struct KeepPolicy {  // TR output: keep (r,c) iff its edge is not marked deleted
@@ -458,9 +457,9 @@ void compact(const P& p, const int64_t* row_off, const uint32_t* tile_lo, uint64
 }
 
 void tile_lo_build(const int64_t* row_off, uint64_t n, uint64_t nnz, uint64_t ntiles,
-                   uint32_t* tile_lo, hipStream_t s) {
+                   uint32_t* tile_lo, hipStream_t s, uint64_t tile) {
   hipLaunchKernelGGL(k_tile_lo, dim3(grid_for(ntiles + 1)), dim3(kBlock), 0, s, row_off, n, nnz,
-                     ntiles, tile_lo);
+                     ntiles, tile, tile_lo);
 }
 
 // DAG: dag_col = rank ids of forward entries; eid for forward entries.
@@ -468,7 +467,8 @@ void orient(const int64_t* row_off, const uint32_t* col, const uint32_t* rank, u
             uint64_t nnz, uint64_t ntiles, const uint32_t* tile_lo, uint32_t* tile_cnt,
             uint64_t* tile_base, uint64_t* scan_tmp, uint32_t* dag_col, uint32_t* eid,
             uint32_t* fstart, hipStream_t s) {
-  OrientPolicy p{col, rank, eid};
+  (void)eid;  // edge ids are assigned after the row sort, by the triangle kernel
+  OrientPolicy p{col, rank};
   compact<OrientPolicy, uint32_t>(p, row_off, tile_lo, n, nnz, ntiles, tile_cnt, tile_base,
                                   scan_tmp, dag_col, nnz / 2, fstart, s);
 }

@@ -1,0 +1,173 @@
+// Sorting DAG rows by rank id (rows longer than kSortMin only).
+//
+// The triangle kernel finds the in-neighbour edge (y,x) inside out(y) by
+// binary search and scans only the part of out(y) ranked above x, which is
+// the suffix of a sorted row.  Short rows are scanned whole, so they need no
+// sort.  Rows of length kSortMin+1..256 are sorted by one wave each, up to
+// 4096 by one block in LDS, longer rows by one block in global memory.
+#include "slim_internal.h"
+
+namespace slim {
+
+constexpr uint32_t kWaveSortMax = 256;
+constexpr uint32_t kBlockSortMax = 4096;
+constexpr uint32_t kPad = 0xffffffffu;  // larger than every rank id (n <= 2^32-1)
+
+__device__ __forceinline__ uint32_t pow2_ceil(uint32_t v) {
+  uint32_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Classify rows: lists[0] gets rows for the wave sort, lists[1] for the block
+// sort, lists[2] for the global sort; counts[0..2] their lengths.
+__global__ void k_sort_classify(const uint2* dag_rng, uint64_t n, uint32_t* wave_list,
+                                uint32_t* block_list, uint32_t* huge_list, uint32_t* counts) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+    const uint64_t x = base + threadIdx.x;
+    uint32_t len = 0;
+    if (x < n) {
+      const uint2 r = dag_rng[x];
+      len = r.y - r.x;
+    }
+    const bool cls[3] = {len > kSortMin && len <= kWaveSortMax,
+                         len > kWaveSortMax && len <= kBlockSortMax, len > kBlockSortMax};
+    uint32_t* lists[3] = {wave_list, block_list, huge_list};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const uint64_t bal = __ballot(cls[c]);
+      if (bal == 0) continue;
+      const uint32_t cnt = __popcll(bal);
+      uint32_t base_idx = 0;
+      const int leader = __ffsll((unsigned long long)bal) - 1;
+      if ((int)lane_id() == leader) base_idx = atomicAdd(&counts[c], cnt);
+      base_idx = __shfl(base_idx, leader, kWave);
+      if (cls[c]) lists[c][base_idx + __popcll(bal & lanemask_lt())] = (uint32_t)x;
+    }
+  }
+}
+
+// One wave per row (kSortMin < len <= 256): bitonic sort in a 1 KB LDS slice.
+__global__ __launch_bounds__(kBlock) void k_sort_wave(const uint2* dag_rng, uint32_t* dag_col,
+                                                      const uint32_t* list,
+                                                      const uint32_t* count) {
+  __shared__ uint32_t buf[kWavesPerBlock][kWaveSortMax];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  uint32_t* s = buf[w];
+  const uint32_t total = *count;
+  for (uint32_t i = blockIdx.x * kWavesPerBlock + w; i < total;
+       i += gridDim.x * kWavesPerBlock) {
+    const uint2 r = dag_rng[list[i]];
+    const uint32_t len = r.y - r.x, P = pow2_ceil(len);
+    for (uint32_t k = lane; k < P; k += kWave) s[k] = k < len ? dag_col[r.x + k] : kPad;
+    wave_sync_lds();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t t = lane; t < P / 2; t += kWave) {
+          const uint32_t a = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // lower index of the pair
+          const uint32_t b = a | j;
+          const bool up = (a & k) == 0;
+          const uint32_t va = s[a], vb = s[b];
+          if ((va > vb) == up) {
+            s[a] = vb;
+            s[b] = va;
+          }
+        }
+        wave_sync_lds();
+      }
+    }
+    for (uint32_t k = lane; k < len; k += kWave) dag_col[r.x + k] = s[k];
+    wave_sync_lds();
+  }
+}
+
+// One block per row (256 < len <= 4096): bitonic sort in LDS.
+__global__ __launch_bounds__(kBlock) void k_sort_block(const uint2* dag_rng, uint32_t* dag_col,
+                                                       const uint32_t* list,
+                                                       const uint32_t* count) {
+  __shared__ uint32_t s[kBlockSortMax];
+  const uint32_t total = *count;
+  for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
+    const uint2 r = dag_rng[list[i]];
+    const uint32_t len = r.y - r.x, P = pow2_ceil(len);
+    for (uint32_t k = threadIdx.x; k < P; k += kBlock) s[k] = k < len ? dag_col[r.x + k] : kPad;
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t t = threadIdx.x; t < P / 2; t += kBlock) {
+          const uint32_t a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+          const uint32_t b = a | j;
+          const bool up = (a & k) == 0;
+          const uint32_t va = s[a], vb = s[b];
+          if ((va > vb) == up) {
+            s[a] = vb;
+            s[b] = va;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (uint32_t k = threadIdx.x; k < len; k += kBlock) dag_col[r.x + k] = s[k];
+    __syncthreads();
+  }
+}
+
+// One block per row (len > 4096): bitonic sort in place in global memory.
+// Every merge is ascending (the first step of a merge pairs i with its mirror
+// i ^ (k-1)), so the virtual +inf padding past `len` never moves and pairs
+// that reach past the end are skipped.
+__global__ __launch_bounds__(1024) void k_sort_huge(const uint2* dag_rng, uint32_t* dag_col,
+                                                    const uint32_t* list,
+                                                    const uint32_t* count) {
+  const uint32_t total = *count;
+  for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
+    const uint2 r = dag_rng[list[i]];
+    uint32_t* a = dag_col + r.x;
+    const uint32_t len = r.y - r.x, P = pow2_ceil(len);
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+          const uint32_t lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+          const uint32_t hi = (j == (k >> 1)) ? (lo ^ (k - 1)) : (lo | j);
+          if (hi < len) {
+            const uint32_t va = a[lo], vb = a[hi];
+            if (va > vb) {
+              a[lo] = vb;
+              a[hi] = va;
+            }
+          }
+        }
+        __threadfence_block();
+        __syncthreads();
+      }
+    }
+  }
+}
+
+void sort_rows(const uint2* dag_rng, uint64_t n, uint32_t* dag_col, uint32_t* lists,
+               uint32_t* counts, int num_cu, hipStream_t s) {
+  fill_u32(counts, 4, 0, s);
+  uint32_t* wave_list = lists;
+  uint32_t* block_list = lists + n;
+  uint32_t* huge_list = lists + 2 * n;
+  unsigned g = (unsigned)((n + kBlock - 1) / kBlock);
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_sort_classify, dim3(g), dim3(kBlock), 0, s, dag_rng, n, wave_list,
+                     block_list, huge_list, counts);
+  hipLaunchKernelGGL(k_sort_wave, dim3(num_cu * 8), dim3(kBlock), 0, s, dag_rng, dag_col,
+                     wave_list, counts + 0);
+  hipLaunchKernelGGL(k_sort_block, dim3(num_cu * 4), dim3(kBlock), 0, s, dag_rng, dag_col,
+                     block_list, counts + 1);
+  hipLaunchKernelGGL(k_sort_huge, dim3(num_cu), dim3(1024), 0, s, dag_rng, dag_col, huge_list,
+                     counts + 2);
+}
+
+}  // namespace slim

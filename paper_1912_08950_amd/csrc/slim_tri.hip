@@ -2,126 +2,540 @@
 // section 4.3: every triangle of the input graph runs kernel `p-1-reduction`
 // once; a selected triangle deletes one uniformly chosen edge).
 //
-// Each triangle {y,x,w} with rank(y) < rank(x) < rank(w) is found exactly
-// once, from its middle vertex x: w lies in out(x) (kept in an LDS hash
-// table) and in out(y) for an in-neighbour y of x (scanned from the DAG).
-// The DAG position of every edge of the triangle is known at that point, so
-// the deletion is an idempotent atomic OR into a bitmap over DAG positions.
-// Selection uses only the id-sorted triple, so the result does not depend
-// on the order in which triangles are found.
+// Vertices are ranked by (degree, id) and every edge points from lower to
+// higher rank.  A triangle y < x < w (in rank) is found exactly once, from
+// its middle vertex x: the edge (y,x) is an in-edge of x, w lies in out(x)
+// and in out(y) above x.  Work is organised over tiles of CSR entries: the
+// rows of a tile are middle vertices, their backward entries are the
+// in-edges, and their out-lists sit in an LDS hash keyed by (w, row).  Each
+// in-edge (y,x) scans the part of out(y) ranked above x -- the suffix after
+// x for a sorted row (binary search), the whole row for a short one -- and
+// the scan items of all in-edges of a batch are spread over the lanes so
+// that loads are contiguous.  Hits go to a per-wave queue and are hashed
+// (Philox4x32-10 of the id-sorted triple) 64 at a time.
+//
+// Deletion marks: (x,w) lies in the tile's own out-lists and is collected
+// in an LDS bitmap; (y,x) is a per-in-edge flag; (y,w) is an atomic OR into
+// the global bitmap over DAG positions.  All marks are idempotent ORs, so
+// the result does not depend on the order in which triangles are found.
 #include "slim_internal.h"
 
 namespace slim {
 
-constexpr int kHashSlots = 4096;  // LDS hash table capacity; out(x) is hashed in
-                                  // passes of at most `chunk` <= kHashSlots/2 entries
+constexpr int kTB = 512;             // threads per block
+constexpr int kTW = kTB / kWave;     // waves per block
+constexpr int kTT = 2048;            // CSR entries per tile
+constexpr int kTC = kTT / kWave;     // 64-entry chunks per tile
+constexpr int kHashCap = 2048;       // out-list entries hashed per pass
+constexpr int kSlots = 4096;         // hash slots (load <= 1/2)
+constexpr int kSlotBits = 12;
+constexpr int kBatch = 320;          // in-edges per batch
+constexpr int kQ = 128;              // per-wave hit queue (records)
+constexpr int kUnroll = 4;           // windows of 64 items issued together
 constexpr uint32_t kEmpty = 0xffffffffu;
 
-__device__ __forceinline__ uint32_t hslot(uint32_t w, int lg) {
-  return (w * 0x9E3779B1u) >> (32 - lg);
+static_assert(kBatch <= kTB, "one thread per in-edge in the setup");
+static_assert(kTC <= kWave, "one wave scans the chunk sums");
+
+struct TriSmem {
+  uint32_t srow[kTT];  // row of each tile entry (after the max-scan)
+  uint32_t cmax[kTC];
+  uint16_t bw[kTT];    // local indices of the tile's backward entries, in order
+  uint32_t fwd[kTT / 32];  // forward entries of the tile (edge ids come from the hash)
+  uint32_t h_w[kSlots];
+  uint32_t h_tag[kSlots];     // (position in hashed range << 16) | row start offset
+  uint32_t xold[kHashCap];    // original id of each hashed out-list entry
+  uint32_t xbits[kHashCap / 32 + 2];
+  uint4 ie[kBatch];           // {scan begin, x rank, y old id, x old id}
+  uint32_t ie_pre[kBatch + 1];
+  uint32_t ie_e[kBatch];      // DAG position of (y,x) (kEmpty until found)
+  uint32_t ie_xj[kBatch];     // (out(x) nonempty << 31) | (row start offset << 16) | CSR index
+  uint32_t ie_flag[(kBatch + 31) / 32];
+  union {
+    uint32_t dpos[kHashCap];  // row start offset of each hashed position
+    uint2 queue[kTW][kQ];     // hit records {item, (in-edge << 16) | slot}
+  } u;
+  uint32_t marker[kTW][kWave];
+  uint32_t wsum[kTW];
+  uint32_t cbase[kTC];
+  uint64_t cmask[kTC];
+  uint32_t bcast[4];
+  uint64_t red[2][kTW];
+};
+
+__device__ __forceinline__ uint32_t hslot(uint32_t w, uint32_t xb) {
+  return ((w ^ (xb * 0x85EBCA6Bu)) * 0x9E3779B1u) >> (32 - kSlotBits);
 }
 
-__global__ __launch_bounds__(kBlock) void k_triangles_v1(TriArgs a, uint32_t kChunkMax) {
-  __shared__ uint32_t hkey[kHashSlots];
-  __shared__ uint32_t hpos[kHashSlots];
-  __shared__ uint32_t hold[kHashSlots];
-  __shared__ uint64_t red[2][kWavesPerBlock];
-  const int tid = threadIdx.x;
-  uint64_t n_tri = 0, n_sel = 0;
-  for (uint64_t x = blockIdx.x; x < a.n; x += gridDim.x) {
-    const uint32_t u0 = a.order[x];
-    const int64_t rb = a.row_off[u0], re = a.row_off[u0 + 1];
-    if (re == rb) continue;  // isolated vertex (block-uniform)
-    const uint2 xr = a.dag_rng[x];
-    const uint32_t ox = xr.y - xr.x;
-    for (uint32_t c0 = 0; c0 == 0 || c0 < ox; c0 += kChunkMax) {
-      const uint32_t clen = ox - c0 < kChunkMax ? ox - c0 : kChunkMax;
-      int lg = 6;
-      while ((1u << lg) < 2 * clen) ++lg;
-      const uint32_t mask = (1u << lg) - 1;
-      for (uint32_t i = tid; i <= mask; i += kBlock) hkey[i] = kEmpty;
-      __syncthreads();
-      for (uint32_t k = tid; k < clen; k += kBlock) {
-        const uint32_t w = a.dag_col[xr.x + c0 + k];
-        uint32_t slot = hslot(w, lg);
-        while (atomicCAS(&hkey[slot], kEmpty, w) != kEmpty) slot = (slot + 1) & mask;
-        hpos[slot] = c0 + k;
-        hold[slot] = a.order[w];
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Row of every entry of the tile [j0, j0 + kTT): srow[i] after the scan.
+__device__ void tri_tile_rows(const int64_t* row_off, int64_t j0, uint32_t lo, uint32_t hi,
+                              TriSmem& S) {
+  const int t = threadIdx.x, w = t / kWave, lane = lane_id();
+  for (int i = t; i < kTT; i += kTB) S.srow[i] = 0;
+  __syncthreads();
+  if (t == 0) S.srow[0] = lo > 0 ? lo - 1 : 0;
+  __syncthreads();
+  for (uint32_t r = lo + t; r < hi; r += kTB) {
+    const int64_t b = row_off[r], e = row_off[r + 1];
+    const int64_t s = b - j0;
+    if (e > b && s >= 0 && s < kTT) S.srow[s] = r;
+  }
+  __syncthreads();
+  for (int c = w; c < kTC; c += kTW) {
+    const uint32_t v = wave_incl_max(S.srow[c * kWave + lane]);
+    S.srow[c * kWave + lane] = v;
+    if (lane == kWave - 1) S.cmax[c] = v;
+  }
+  __syncthreads();
+  if (w == 0) {
+    const uint32_t v = lane < kTC ? S.cmax[lane] : 0;
+    const uint32_t incl = wave_incl_max(v);
+    uint32_t excl = __shfl_up(incl, 1, kWave);
+    if (lane == 0) excl = 0;
+    if (lane < kTC) S.cmax[lane] = excl;
+  }
+  __syncthreads();
+  for (int i = t; i < kTT; i += kTB) {
+    const uint32_t a = S.srow[i], b = S.cmax[i >> 6];
+    S.srow[i] = a > b ? a : b;
+  }
+  __syncthreads();
+}
+
+struct TriCtx {
+  TriArgs a;
+  uint32_t cap;   // out-list entries hashed per pass (<= kHashCap)
+  int64_t j0;
+  uint32_t D0;    // first DAG position of the hashed range
+  uint32_t hlen;  // number of hashed entries
+  uint64_t n_tri, n_sel;
+};
+
+// Hash the out-list entries [D0, D0 + len) under key (w, row start offset);
+// the offset comes from dpos (all rows of the tile) or is 0 (one row).
+__device__ void tri_build_hash(TriCtx& C, TriSmem& S, uint32_t len, bool use_dpos) {
+  for (int i = threadIdx.x; i < kSlots; i += kTB) S.h_w[i] = kEmpty;
+  for (int i = threadIdx.x; i < kHashCap / 32 + 2; i += kTB) S.xbits[i] = 0;
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < len; q += kTB) {
+    const uint32_t w = C.a.dag_col[C.D0 + q];
+    const uint32_t xb = use_dpos ? S.u.dpos[q] : 0u;
+    uint32_t slot = hslot(w, xb);
+    while (atomicCAS(&S.h_w[slot], kEmpty, w) != kEmpty) slot = (slot + 1) & (kSlots - 1);
+    S.h_tag[slot] = (q << 16) | xb;
+    S.xold[q] = C.a.order[w];
+  }
+  C.hlen = len;
+  __syncthreads();
+}
+
+__device__ void tri_flush_xbits(TriCtx& C, TriSmem& S) {
+  __syncthreads();
+  const uint32_t nwords = (C.D0 % 32 + C.hlen + 31) / 32;
+  const uint32_t base = C.D0 / 32;
+  for (uint32_t i = threadIdx.x; i < nwords; i += kTB) {
+    const uint32_t v = S.xbits[i];
+    if (v)
+      __hip_atomic_fetch_or(C.a.del + base + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+}
+
+// Forward entries among tile entries [ia, ib): their edge is in out(x) of the
+// entry's own row, so the DAG position comes from the hash (a miss means the
+// entry lies in another pass of a split row).
+__device__ void tri_forward_eids(TriCtx& C, TriSmem& S, uint32_t ia, uint32_t ib,
+                                 bool all_rows) {
+  if (C.hlen == 0) return;
+  for (uint32_t i = ia + threadIdx.x; i < ib; i += kTB) {
+    if (!(S.fwd[i >> 5] & (1u << (i & 31)))) continue;
+    const uint64_t j = (uint64_t)C.j0 + i;
+    const uint32_t w = C.a.rank[C.a.col[j]];
+    const uint32_t xb = all_rows ? C.a.fstart[S.srow[i]] - C.D0 : 0u;
+    uint32_t slot = hslot(w, xb);
+    for (;;) {
+      const uint32_t hw = S.h_w[slot];
+      if (hw == kEmpty) break;
+      const uint32_t tag = S.h_tag[slot];
+      if (hw == w && (tag & 0xffffu) == xb) {
+        C.a.eid[j] = C.D0 + (tag >> 16);
+        break;
       }
-      __syncthreads();
-      for (int64_t j = rb + tid; j < re; j += kBlock) {
-        const uint32_t c = a.col[j];
-        const uint32_t y = a.rank[c];
-        if (y >= x) continue;  // forward entry: not an in-edge of x
-        const uint2 yr = a.dag_rng[y];
-        uint32_t e_yx = kEmpty;
-        bool del_yx = false;
-        for (uint32_t i = yr.x; i < yr.y; ++i) {
-          const uint32_t w = a.dag_col[i];
-          if (w == x) {
-            e_yx = i;
-            continue;
-          }
-          if (w < x || clen == 0) continue;
-          uint32_t slot = hslot(w, lg), hk;
-          for (;;) {
-            hk = hkey[slot];
-            if (hk == w || hk == kEmpty) break;
-            slot = (slot + 1) & mask;
-          }
-          if (hk != w) continue;
-          // triangle {c, u0, ow} in original ids
-          const uint32_t ow = hold[slot];
-          const uint32_t kpos = hpos[slot];
-          ++n_tri;
-          uint32_t t0 = c, t1 = u0, t2 = ow;
-          sort3(t0, t1, t2);
-          uint32_t w0, w1;
-          philox_w01(t0, t1, t2, 0u, a.k0, a.k1, w0, w1);
-          if ((uint64_t)w0 < a.thr) {
-            ++n_sel;
-            const uint32_t kk = __umulhi(w1, 3u);  // 0:{t0,t1} 1:{t0,t2} 2:{t1,t2}
-            const uint32_t excl = kk == 0 ? t2 : (kk == 1 ? t1 : t0);
-            if (excl == ow)
-              del_yx = true;  // edge {c,u0} = (y,x)
-            else if (excl == u0)
-              bit_set(a.del, i);  // edge {c,ow} = (y,w)
-            else
-              bit_set(a.del, xr.x + kpos);  // edge {u0,ow} = (x,w)
-          }
-        }
-        if (c0 == 0) a.eid[j] = e_yx;
-        if (del_yx && e_yx != kEmpty) bit_set(a.del, e_yx);
-      }
-      __syncthreads();
+      slot = (slot + 1) & (kSlots - 1);
     }
   }
-  const int w = tid / kWave;
-  n_tri = wave_sum64(n_tri);
-  n_sel = wave_sum64(n_sel);
-  if (lane_id() == 0) {
-    red[0][w] = n_tri;
-    red[1][w] = n_sel;
+}
+
+// Hash, select and mark the queued hits q[head .. head + cnt) (cnt <= 64).
+__device__ void tri_drain(TriCtx& C, TriSmem& S, const uint2* q, uint32_t head, uint32_t cnt) {
+  const uint32_t lane = lane_id();
+  if (lane < cnt) {
+    const uint2 rec = q[(head + lane) % kQ];
+    const uint32_t k = rec.y >> 16, slot = rec.y & 0xffffu;
+    const uint4 ie = S.ie[k];
+    const uint32_t p_yw = ie.x + (rec.x - S.ie_pre[k]);
+    const uint32_t qpos = S.h_tag[slot] >> 16;
+    const uint32_t ow = S.xold[qpos];
+    const uint32_t c = ie.z, u0 = ie.w;
+    uint32_t t0 = c, t1 = u0, t2 = ow;
+    sort3(t0, t1, t2);
+    uint32_t w0, w1;
+    philox_w01(t0, t1, t2, 0u, C.a.k0, C.a.k1, w0, w1);
+    C.n_tri += 1;
+    if ((uint64_t)w0 < C.a.thr) {
+      C.n_sel += 1;
+      const uint32_t kk = __umulhi(w1, 3u);  // 0:{t0,t1} 1:{t0,t2} 2:{t1,t2}
+      const uint32_t excl = kk == 0 ? t2 : (kk == 1 ? t1 : t0);
+      if (excl == ow) {  // edge {y,x}: flag of the in-edge
+        atomicOr(&S.ie_flag[k >> 5], 1u << (k & 31));
+      } else if (excl == c) {  // edge {x,w}: position qpos of the hashed range
+        const uint32_t bit = C.D0 % 32 + qpos;
+        atomicOr(&S.xbits[bit >> 5], 1u << (bit & 31));
+      } else {  // edge {y,w}: global bitmap
+        if (!bit_get(C.a.del, p_yw)) bit_set(C.a.del, p_yw);
+      }
+    }
+  }
+}
+
+// Process the in-edges bw[b0, b1) of the tile against the current hash.
+__device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool all_rows) {
+  const int tid = threadIdx.x, w = tid / kWave;
+  const uint32_t lane = lane_id();
+  const uint32_t nin = b1 - b0;
+  // ---- setup: one thread per in-edge
+  uint32_t cnt = 0;
+  if ((uint32_t)tid < nin) {
+    const uint32_t i = S.bw[b0 + tid];
+    const uint64_t j = (uint64_t)C.j0 + i;
+    const uint32_t r = S.srow[i];
+    const uint32_t c = C.a.col[j];
+    const uint32_t y = C.a.rank[c];
+    const uint32_t x = C.a.rank[r];
+    const uint2 yr = C.a.dag_rng[y];
+    const uint32_t fs = C.a.fstart[r], fe = C.a.fstart[r + 1];
+    uint32_t beg = yr.x, e = kEmpty;
+    if (yr.y - yr.x > kSortMin) {  // sorted row: x by binary search
+      uint32_t lo = yr.x, hi = yr.y;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (C.a.dag_col[mid] < x)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      e = lo;
+      beg = lo + 1;
+      if (fe == fs) beg = yr.y;  // out(x) empty: no triangle, nothing to scan
+    }
+    cnt = yr.y - beg;
+    // An empty out(x) starts where the next row starts, so its row offset is
+    // not a unique tag: in-edges into it must not probe at all.
+    const uint32_t xb = all_rows ? (fs - C.D0) : 0u;
+    S.ie[tid] = make_uint4(beg, x, c, r);
+    S.ie_e[tid] = e;
+    S.ie_xj[tid] = (fe > fs ? 0x80000000u : 0u) | (xb << 16) | i;
+  }
+  if ((uint32_t)tid < (kBatch + 31) / 32) S.ie_flag[tid] = 0;
+  {  // block exclusive scan of cnt into ie_pre
+    const uint64_t incl = wave_incl_sum64(cnt);
+    if (lane == kWave - 1) S.wsum[w] = (uint32_t)incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int i = 0; i < kTW; ++i) {
+      if (i < w) before += S.wsum[i];
+      all += S.wsum[i];
+    }
+    if ((uint32_t)tid < nin) S.ie_pre[tid] = before + (uint32_t)incl - cnt;
+    if (tid == 0) S.ie_pre[nin] = all;
+    __syncthreads();
+  }
+  const uint32_t W = S.ie_pre[nin];
+  // ---- items: wave w takes the contiguous range [ws, we)
+  const uint32_t ws = (uint32_t)(((uint64_t)W * w) / kTW);
+  const uint32_t we = (uint32_t)(((uint64_t)W * (w + 1)) / kTW);
+  uint2* q = S.u.queue[w];
+  uint32_t* mk = S.marker[w];
+  uint32_t qhead = 0, qcnt = 0;
+  uint32_t kcur = 0;
+  if (ws < we) {  // in-edge holding item ws: last k with ie_pre[k] <= ws
+    uint32_t lo = 0, hi = nin;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (S.ie_pre[mid] <= ws)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    kcur = lo;
+  }
+  for (uint32_t wb = ws; wb < we; wb += kWave * kUnroll) {
+    uint32_t kk[kUnroll], tt[kUnroll], wv[kUnroll];
+    bool valid[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const uint32_t base = wb + u * kWave;
+      tt[u] = base + lane;
+      valid[u] = tt[u] < we;
+      uint32_t k = kcur;
+      if (base < we) {
+        // does another in-edge start inside [base, base + 64)?
+        const uint32_t nxt = kcur + 1 < nin ? S.ie_pre[kcur + 1] : 0xffffffffu;
+        if (nxt < base + kWave) {
+          mk[lane] = 0;
+          wave_sync();
+          if (lane == 0) mk[0] = kcur;
+          wave_sync();
+          for (uint32_t cand0 = kcur + 1;; cand0 += kWave) {
+            const uint32_t cand = cand0 + lane;
+            const uint32_t s = cand < nin ? S.ie_pre[cand] : 0xffffffffu;
+            if (s < base + kWave) atomicMax(&mk[s - base], cand);
+            const uint32_t last = cand0 + kWave - 1;
+            if (!(last < nin && S.ie_pre[last] < base + kWave)) break;
+          }
+          wave_sync();
+          k = wave_incl_max(mk[lane]);
+          wave_sync();
+        }
+        kcur = __shfl(k, kWave - 1, kWave);
+      }
+      kk[u] = k;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      wv[u] = kEmpty;
+      if (valid[u]) wv[u] = C.a.dag_col[S.ie[kk[u]].x + (tt[u] - S.ie_pre[kk[u]])];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      bool hit = false;
+      uint32_t slot = 0;
+      if (valid[u]) {
+        const uint32_t k = kk[u];
+        const uint32_t x = S.ie[k].y;
+        const uint32_t wq = wv[u];
+        if (wq == x) {
+          S.ie_e[k] = S.ie[k].x + (tt[u] - S.ie_pre[k]);
+        } else if (wq > x && (S.ie_xj[k] & 0x80000000u)) {
+          const uint32_t xb = (S.ie_xj[k] >> 16) & 0x7fffu;
+          slot = hslot(wq, xb);
+          for (;;) {
+            const uint32_t hw = S.h_w[slot];
+            if (hw == kEmpty) break;
+            if (hw == wq && (S.h_tag[slot] & 0xffffu) == xb) {
+              hit = true;
+              break;
+            }
+            slot = (slot + 1) & (kSlots - 1);
+          }
+        }
+      }
+      const uint64_t bal = __ballot(hit);
+      if (bal) {
+        if (hit)
+          q[(qhead + qcnt + __popcll(bal & lanemask_lt())) % kQ] =
+              make_uint2(tt[u], (kk[u] << 16) | slot);
+        qcnt += __popcll(bal);
+        if (qcnt >= (uint32_t)kWave) {
+          wave_sync();
+          tri_drain(C, S, q, qhead, kWave);
+          qhead = (qhead + kWave) % kQ;
+          qcnt -= kWave;
+        }
+      }
+    }
+  }
+  if (qcnt) {
+    wave_sync();
+    tri_drain(C, S, q, qhead, qcnt);
+  }
+  __syncthreads();
+  // ---- finish: eid of every in-edge, (y,x) marks
+  if ((uint32_t)tid < nin) {
+    const uint32_t e = S.ie_e[tid];
+    const uint32_t i = S.ie_xj[tid] & 0xffffu;
+    if (e != kEmpty) {
+      C.a.eid[(uint64_t)C.j0 + i] = e;
+      if (S.ie_flag[tid >> 5] & (1u << (tid & 31))) bit_set(C.a.del, e);
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kTB) void k_triangles(TriArgs a, const uint32_t* tlo,
+                                                   uint64_t ntiles, uint32_t* tile_ctr,
+                                                   uint32_t cap) {
+  __shared__ TriSmem S;
+  TriCtx C;
+  C.a = a;
+  C.cap = cap;
+  C.n_tri = 0;
+  C.n_sel = 0;
+  const int tid = threadIdx.x, w = tid / kWave;
+  const uint32_t lane = lane_id();
+  const uint64_t nnz = a.nnz;
+  for (;;) {
+    if (tid == 0) S.bcast[0] = atomicAdd(tile_ctr, 1u);
+    __syncthreads();
+    const uint64_t t = S.bcast[0];
+    __syncthreads();
+    if (t >= ntiles) break;
+    const int64_t j0 = (int64_t)(t * kTT);
+    const uint32_t span = (uint32_t)((uint64_t)j0 + kTT <= nnz ? kTT : nnz - j0);
+    C.j0 = j0;
+    tri_tile_rows(a.row_off, j0, tlo[t], tlo[t + 1], S);
+    // ---- backward entries (the in-edges of the tile's rows), in CSR order
+    uint32_t fb = 0;
+    for (int k = 0; k < kTC / kTW; ++k) {
+      const int c = w + k * kTW;
+      const uint32_t i = c * kWave + lane;
+      bool f = false, g = false;
+      if (i < span) {
+        const uint32_t rc = a.rank[a.col[j0 + i]], rr = a.rank[S.srow[i]];
+        f = rc < rr;
+        g = rc > rr;
+      }
+      const uint64_t m = __ballot(f);
+      const uint64_t mf = __ballot(g);
+      if (lane == 0) {
+        S.cmask[c] = m;
+        S.fwd[2 * c] = (uint32_t)mf;
+        S.fwd[2 * c + 1] = (uint32_t)(mf >> 32);
+      }
+      if (f) fb |= 1u << k;
+    }
+    __syncthreads();
+    if (w == 0) {
+      const uint32_t v = lane < kTC ? __popcll(S.cmask[lane]) : 0;
+      const uint64_t incl = wave_incl_sum64(v);
+      if (lane < kTC) S.cbase[lane] = (uint32_t)(incl - v);
+      if (lane == kWave - 1) S.bcast[1] = (uint32_t)incl;
+    }
+    __syncthreads();
+    for (int k = 0; k < kTC / kTW; ++k) {
+      if (fb & (1u << k)) {
+        const int c = w + k * kTW;
+        S.bw[S.cbase[c] + __popcll(S.cmask[c] & lanemask_lt())] = (uint16_t)(c * kWave + lane);
+      }
+    }
+    const uint32_t nbw = S.bcast[1];
+    __syncthreads();
+    const uint32_t r_lo = S.srow[0], r_hi = S.srow[span - 1];
+    const uint32_t D0 = a.fstart[r_lo], D1 = a.fstart[r_hi + 1];
+    if (D1 - D0 <= C.cap) {
+      // ---- all rows of the tile share one hash
+      const uint32_t len = D1 - D0;
+      for (uint32_t i = tid; i < len; i += kTB) S.u.dpos[i] = 0;
+      __syncthreads();
+      for (uint32_t r = r_lo + tid; r <= r_hi; r += kTB) {
+        const uint32_t fs = a.fstart[r], fe = a.fstart[r + 1];
+        if (fe > fs) S.u.dpos[fs - D0] = fs - D0;
+      }
+      __syncthreads();
+      const uint32_t nc = (len + kWave - 1) / kWave;
+      for (uint32_t c = w; c < nc; c += kTW) {  // max-scan: chunk scans, then carry
+        const uint32_t i = c * kWave + lane;
+        const uint32_t v = wave_incl_max(i < len ? S.u.dpos[i] : 0u);
+        if (i < len) S.u.dpos[i] = v;
+        if (lane == kWave - 1) S.cbase[c] = v;
+      }
+      __syncthreads();
+      if (w == 0) {
+        const uint32_t v = lane < nc ? S.cbase[lane] : 0;
+        const uint32_t incl = wave_incl_max(v);
+        uint32_t excl = __shfl_up(incl, 1, kWave);
+        if (lane == 0) excl = 0;
+        if (lane < nc) S.cbase[lane] = excl;
+      }
+      __syncthreads();
+      for (uint32_t i = tid; i < len; i += kTB) {
+        const uint32_t v = S.u.dpos[i], cb = S.cbase[i >> 6];
+        S.u.dpos[i] = v > cb ? v : cb;
+      }
+      __syncthreads();
+      C.D0 = D0;
+      tri_build_hash(C, S, len, true);
+      tri_forward_eids(C, S, 0, span, true);
+      for (uint32_t b0 = 0; b0 < nbw; b0 += kBatch)
+        tri_batch(C, S, b0, b0 + kBatch < nbw ? b0 + kBatch : nbw, true);
+      tri_flush_xbits(C, S);
+    } else {
+      // ---- one row at a time, its out-list hashed in passes of C.cap entries
+      uint32_t cur = 0;
+      for (uint32_t r = r_lo; r <= r_hi; ++r) {
+        const int64_t rb = a.row_off[r], re = a.row_off[r + 1];
+        const uint32_t ea = (uint32_t)((rb > j0 ? rb : j0) - j0);
+        const uint32_t eb = (uint32_t)((re < j0 + (int64_t)span ? re : j0 + (int64_t)span) - j0);
+        if (eb <= ea) continue;
+        if (tid == 0) {  // first bw index at or past the end of row r in the tile
+          uint32_t lo = cur, hi = nbw;
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((uint32_t)S.bw[mid] < eb)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+          S.bcast[2] = lo;
+        }
+        __syncthreads();
+        const uint32_t bh = S.bcast[2];
+        __syncthreads();
+        const uint32_t xb = a.fstart[r], xe = a.fstart[r + 1];
+        if (xe > xb || bh > cur) {
+          for (uint32_t cb = xb; cb == xb || cb < xe; cb += C.cap) {
+            const uint32_t len = xe - cb < C.cap ? xe - cb : C.cap;
+            C.D0 = cb;
+            tri_build_hash(C, S, len, false);
+            tri_forward_eids(C, S, ea, eb, false);
+            for (uint32_t b0 = cur; b0 < bh; b0 += kBatch)
+              tri_batch(C, S, b0, b0 + kBatch < bh ? b0 + kBatch : bh, false);
+            tri_flush_xbits(C, S);
+          }
+        }
+        cur = bh;
+      }
+    }
+  }
+  // ---- counters
+  const uint64_t s0 = wave_sum64(C.n_tri), s1 = wave_sum64(C.n_sel);
+  if (lane == 0) {
+    S.red[0][w] = s0;
+    S.red[1][w] = s1;
   }
   __syncthreads();
   if (tid == 0) {
-    uint64_t s0 = 0, s1 = 0;
-    for (int i = 0; i < kWavesPerBlock; ++i) {
-      s0 += red[0][i];
-      s1 += red[1][i];
+    uint64_t t0 = 0, t1 = 0;
+    for (int i = 0; i < kTW; ++i) {
+      t0 += S.red[0][i];
+      t1 += S.red[1][i];
     }
-    if (s0) atomicAdd((unsigned long long*)&a.counters[0], (unsigned long long)s0);
-    if (s1) atomicAdd((unsigned long long*)&a.counters[1], (unsigned long long)s1);
+    if (t0) atomicAdd((unsigned long long*)&a.counters[0], (unsigned long long)t0);
+    if (t1) atomicAdd((unsigned long long*)&a.counters[1], (unsigned long long)t1);
   }
 }
 
-void triangles(const TriArgs& a, int num_cu, hipStream_t s) {
+uint64_t tri_tiles(uint64_t nnz) { return (nnz + kTT - 1) / kTT; }
+uint64_t tri_tile_entries() { return kTT; }
+
+void triangles(const TriArgs& a, const uint32_t* tlo, uint32_t* tile_ctr, int num_cu,
+               hipStream_t s) {
+  const uint64_t ntiles = tri_tiles(a.nnz);
   const Tuning& t = tuning();
   uint64_t blocks = (uint64_t)num_cu * t.tri_blocks_per_cu;
-  if (blocks > a.n) blocks = a.n;
+  if (blocks > ntiles) blocks = ntiles;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_triangles_v1, dim3((unsigned)blocks), dim3(kBlock), 0, s, a,
-                     (uint32_t)t.tri_chunk);
+  fill_u32(tile_ctr, 1, 0, s);
+  uint32_t cap = (uint32_t)t.tri_chunk;
+  if (cap > (uint32_t)kHashCap) cap = kHashCap;
+  hipLaunchKernelGGL(k_triangles, dim3((unsigned)blocks), dim3(kTB), 0, s, a, tlo, ntiles,
+                     tile_ctr, cap);
 }
 
 }  // namespace slim
