@@ -15,18 +15,19 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wal
          "-fvisibility=hidden"]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into paper_1912_08950_amd/libslim.so."""
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile every HIP source into paper_1912_08950_amd/libslim.so (or
+    `out`, with extra -D `defines`, for variant builds)."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *srcs, "-o", tmp]
+    tmp = out + ".tmp"
+    cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -27,11 +27,14 @@ constexpr int kTW = kTB / kWave;     // waves per block
 constexpr int kTT = 2048;            // CSR entries per tile
 constexpr int kTC = kTT / kWave;     // 64-entry chunks per tile
 constexpr int kHashCap = 2048;       // out-list entries hashed per pass
-constexpr int kSlots = 4096;         // hash slots (load <= 1/2)
-constexpr int kSlotBits = 12;
+constexpr int kBuckets = 2048;       // hash buckets of two slots (load <= 1/2)
+constexpr int kBucketBits = 11;
 constexpr int kBatch = 320;          // in-edges per batch
 constexpr int kQ = 128;              // per-wave hit queue (records)
-constexpr int kUnroll = 4;           // windows of 64 items issued together
+#ifndef SLIM_TRI_UNROLL
+#define SLIM_TRI_UNROLL 4
+#endif
+constexpr int kUnroll = SLIM_TRI_UNROLL;  // windows of 64 items issued together
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 static_assert(kBatch <= kTB, "one thread per in-edge in the setup");
@@ -42,8 +45,7 @@ struct TriSmem {
   uint32_t cmax[kTC];
   uint16_t bw[kTT];    // local indices of the tile's backward entries, in order
   uint32_t fwd[kTT / 32];  // forward entries of the tile (edge ids come from the hash)
-  uint32_t h_w[kSlots];
-  uint32_t h_tag[kSlots];     // (position in hashed range << 16) | row start offset
+  uint4 hb[kBuckets];         // two slots {w, tag}; tag = (position in range << 16) | row offset
   uint32_t xold[kHashCap];    // original id of each hashed out-list entry
   uint32_t xbits[kHashCap / 32 + 2];
   uint4 ie[kBatch];           // {scan begin, x rank, y old id, x old id}
@@ -53,9 +55,8 @@ struct TriSmem {
   uint32_t ie_flag[(kBatch + 31) / 32];
   union {
     uint32_t dpos[kHashCap];  // row start offset of each hashed position
-    uint2 queue[kTW][kQ];     // hit records {item, (in-edge << 16) | slot}
+    uint2 queue[kTW][kQ];     // hit records {item, (in-edge << 16) | position in range}
   } u;
-  uint32_t marker[kTW][kWave];
   uint32_t wsum[kTW];
   uint32_t cbase[kTC];
   uint64_t cmask[kTC];
@@ -63,8 +64,28 @@ struct TriSmem {
   uint64_t red[2][kTW];
 };
 
-__device__ __forceinline__ uint32_t hslot(uint32_t w, uint32_t xb) {
-  return ((w ^ (xb * 0x85EBCA6Bu)) * 0x9E3779B1u) >> (32 - kSlotBits);
+__device__ __forceinline__ uint32_t hbucket(uint32_t w, uint32_t xb) {
+  return ((w ^ (xb * 0x85EBCA6Bu)) * 0x9E3779B1u) >> (32 - kBucketBits);
+}
+
+// Look up (w, row offset xb) starting at bucket b.  Slots fill in probe
+// order and are never removed, so a bucket with a free slot ends the probe.
+__device__ __forceinline__ bool hlookup(const uint4* hb, uint32_t w, uint32_t xb,
+                                        uint32_t& qpos) {
+  uint32_t b = hbucket(w, xb);
+  for (;;) {
+    const uint4 e = hb[b];
+    if (e.x == w && (e.y & 0xffffu) == xb) {
+      qpos = e.y >> 16;
+      return true;
+    }
+    if (e.z == w && (e.w & 0xffffu) == xb) {
+      qpos = e.w >> 16;
+      return true;
+    }
+    if (e.z == kEmpty) return false;
+    b = (b + 1) & (kBuckets - 1);
+  }
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -120,15 +141,26 @@ struct TriCtx {
 // Hash the out-list entries [D0, D0 + len) under key (w, row start offset);
 // the offset comes from dpos (all rows of the tile) or is 0 (one row).
 __device__ void tri_build_hash(TriCtx& C, TriSmem& S, uint32_t len, bool use_dpos) {
-  for (int i = threadIdx.x; i < kSlots; i += kTB) S.h_w[i] = kEmpty;
+  for (int i = threadIdx.x; i < kBuckets; i += kTB)
+    S.hb[i] = make_uint4(kEmpty, 0u, kEmpty, 0u);
   for (int i = threadIdx.x; i < kHashCap / 32 + 2; i += kTB) S.xbits[i] = 0;
   __syncthreads();
+  uint32_t* hw = reinterpret_cast<uint32_t*>(S.hb);
   for (uint32_t q = threadIdx.x; q < len; q += kTB) {
     const uint32_t w = C.a.dag_col[C.D0 + q];
     const uint32_t xb = use_dpos ? S.u.dpos[q] : 0u;
-    uint32_t slot = hslot(w, xb);
-    while (atomicCAS(&S.h_w[slot], kEmpty, w) != kEmpty) slot = (slot + 1) & (kSlots - 1);
-    S.h_tag[slot] = (q << 16) | xb;
+    uint32_t b = hbucket(w, xb);
+    for (;;) {
+      if (atomicCAS(&hw[4 * b], kEmpty, w) == kEmpty) {
+        hw[4 * b + 1] = (q << 16) | xb;
+        break;
+      }
+      if (atomicCAS(&hw[4 * b + 2], kEmpty, w) == kEmpty) {
+        hw[4 * b + 3] = (q << 16) | xb;
+        break;
+      }
+      b = (b + 1) & (kBuckets - 1);
+    }
     S.xold[q] = C.a.order[w];
   }
   C.hlen = len;
@@ -158,50 +190,46 @@ __device__ void tri_forward_eids(TriCtx& C, TriSmem& S, uint32_t ia, uint32_t ib
     const uint64_t j = (uint64_t)C.j0 + i;
     const uint32_t w = C.a.rank[C.a.col[j]];
     const uint32_t xb = all_rows ? C.a.fstart[S.srow[i]] - C.D0 : 0u;
-    uint32_t slot = hslot(w, xb);
-    for (;;) {
-      const uint32_t hw = S.h_w[slot];
-      if (hw == kEmpty) break;
-      const uint32_t tag = S.h_tag[slot];
-      if (hw == w && (tag & 0xffffu) == xb) {
-        C.a.eid[j] = C.D0 + (tag >> 16);
-        break;
-      }
-      slot = (slot + 1) & (kSlots - 1);
-    }
+    uint32_t qpos;
+    if (hlookup(S.hb, w, xb, qpos)) C.a.eid[j] = C.D0 + qpos;
   }
 }
 
-// Hash, select and mark the queued hits q[head .. head + cnt) (cnt <= 64).
-__device__ void tri_drain(TriCtx& C, TriSmem& S, const uint2* q, uint32_t head, uint32_t cnt) {
+// Hash, select and mark the queued hits q[head .. head + cnt) (cnt <= 64);
+// one lane per hit.  Returns 1 in lanes whose triangle was selected.
+__device__ __forceinline__ uint32_t tri_drain(uint32_t* del, uint64_t thr, uint32_t k0,
+                                                        uint32_t k1, TriSmem* Sp,
+                                                        const uint2* q, uint32_t head,
+                                                        uint32_t cnt, uint32_t D0) {
+  TriSmem& S = *Sp;
   const uint32_t lane = lane_id();
+  uint32_t sel = 0;
   if (lane < cnt) {
     const uint2 rec = q[(head + lane) % kQ];
-    const uint32_t k = rec.y >> 16, slot = rec.y & 0xffffu;
+    const uint32_t k = rec.y >> 16, qpos = rec.y & 0xffffu;
     const uint4 ie = S.ie[k];
     const uint32_t p_yw = ie.x + (rec.x - S.ie_pre[k]);
-    const uint32_t qpos = S.h_tag[slot] >> 16;
     const uint32_t ow = S.xold[qpos];
     const uint32_t c = ie.z, u0 = ie.w;
     uint32_t t0 = c, t1 = u0, t2 = ow;
     sort3(t0, t1, t2);
     uint32_t w0, w1;
-    philox_w01(t0, t1, t2, 0u, C.a.k0, C.a.k1, w0, w1);
-    C.n_tri += 1;
-    if ((uint64_t)w0 < C.a.thr) {
-      C.n_sel += 1;
+    philox_w01(t0, t1, t2, 0u, k0, k1, w0, w1);
+    if ((uint64_t)w0 < thr) {
+      sel = 1;
       const uint32_t kk = __umulhi(w1, 3u);  // 0:{t0,t1} 1:{t0,t2} 2:{t1,t2}
       const uint32_t excl = kk == 0 ? t2 : (kk == 1 ? t1 : t0);
       if (excl == ow) {  // edge {y,x}: flag of the in-edge
         atomicOr(&S.ie_flag[k >> 5], 1u << (k & 31));
       } else if (excl == c) {  // edge {x,w}: position qpos of the hashed range
-        const uint32_t bit = C.D0 % 32 + qpos;
+        const uint32_t bit = D0 % 32 + qpos;
         atomicOr(&S.xbits[bit >> 5], 1u << (bit & 31));
       } else {  // edge {y,w}: global bitmap
-        if (!bit_get(C.a.del, p_yw)) bit_set(C.a.del, p_yw);
+        if (!bit_get(del, p_yw)) bit_set(del, p_yw);
       }
     }
   }
+  return sel;
 }
 
 // Process the in-edges bw[b0, b1) of the tile against the current hash.
@@ -257,11 +285,12 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     __syncthreads();
   }
   const uint32_t W = S.ie_pre[nin];
-  // ---- items: wave w takes the contiguous range [ws, we)
+  // ---- items: wave w takes the contiguous range [ws, we).  The current
+  // in-edge's fields stay in scalar registers; a window of 64 items crosses
+  // an in-edge boundary only now and then (a short scalar loop).
   const uint32_t ws = (uint32_t)(((uint64_t)W * w) / kTW);
   const uint32_t we = (uint32_t)(((uint64_t)W * (w + 1)) / kTW);
   uint2* q = S.u.queue[w];
-  uint32_t* mk = S.marker[w];
   uint32_t qhead = 0, qcnt = 0;
   uint32_t kcur = 0;
   if (ws < we) {  // in-edge holding item ws: last k with ie_pre[k] <= ws
@@ -275,64 +304,79 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     }
     kcur = lo;
   }
+  kcur = __builtin_amdgcn_readfirstlane(kcur);
+  uint32_t c_bmp, c_x, c_xj, c_nxt;  // scan begin - item base, x rank, tag word, next start
+  auto fetch = [&](uint32_t k) {
+    const uint4 ie = S.ie[k];
+    c_bmp = __builtin_amdgcn_readfirstlane(ie.x - S.ie_pre[k]);
+    c_x = __builtin_amdgcn_readfirstlane(ie.y);
+    c_xj = __builtin_amdgcn_readfirstlane(S.ie_xj[k]);
+    c_nxt = __builtin_amdgcn_readfirstlane(S.ie_pre[k + 1]);
+  };
+  fetch(kcur);
   for (uint32_t wb = ws; wb < we; wb += kWave * kUnroll) {
-    uint32_t kk[kUnroll], tt[kUnroll], wv[kUnroll];
-    bool valid[kUnroll];
+    uint32_t kk[kUnroll], bm[kUnroll], xx[kUnroll], xj[kUnroll], wv[kUnroll], tt[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const uint32_t base = wb + u * kWave;
-      tt[u] = base + lane;
-      valid[u] = tt[u] < we;
-      uint32_t k = kcur;
-      if (base < we) {
-        // does another in-edge start inside [base, base + 64)?
-        const uint32_t nxt = kcur + 1 < nin ? S.ie_pre[kcur + 1] : 0xffffffffu;
-        if (nxt < base + kWave) {
-          mk[lane] = 0;
-          wave_sync();
-          if (lane == 0) mk[0] = kcur;
-          wave_sync();
-          for (uint32_t cand0 = kcur + 1;; cand0 += kWave) {
-            const uint32_t cand = cand0 + lane;
-            const uint32_t s = cand < nin ? S.ie_pre[cand] : 0xffffffffu;
-            if (s < base + kWave) atomicMax(&mk[s - base], cand);
-            const uint32_t last = cand0 + kWave - 1;
-            if (!(last < nin && S.ie_pre[last] < base + kWave)) break;
-          }
-          wave_sync();
-          k = wave_incl_max(mk[lane]);
-          wave_sync();
+      const uint32_t t = base + lane;
+      uint32_t k = kcur, b = c_bmp, x = c_x, j = c_xj;
+      while (c_nxt < base + kWave && c_nxt < we) {  // in-edge boundaries in this window
+        const uint32_t bound = c_nxt;
+        ++kcur;
+        fetch(kcur);
+        if (t >= bound) {
+          k = kcur;
+          b = c_bmp;
+          x = c_x;
+          j = c_xj;
         }
-        kcur = __shfl(k, kWave - 1, kWave);
       }
+      tt[u] = t;
       kk[u] = k;
+      bm[u] = b;
+      xx[u] = x;
+      xj[u] = j;
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      wv[u] = kEmpty;
-      if (valid[u]) wv[u] = C.a.dag_col[S.ie[kk[u]].x + (tt[u] - S.ie_pre[kk[u]])];
-    }
+    for (int u = 0; u < kUnroll; ++u)
+      wv[u] = tt[u] < we ? C.a.dag_col[bm[u] + tt[u]] : kEmpty;
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      bool hit = false;
-      uint32_t slot = 0;
-      if (valid[u]) {
-        const uint32_t k = kk[u];
-        const uint32_t x = S.ie[k].y;
-        const uint32_t wq = wv[u];
-        if (wq == x) {
-          S.ie_e[k] = S.ie[k].x + (tt[u] - S.ie_pre[k]);
-        } else if (wq > x && (S.ie_xj[k] & 0x80000000u)) {
-          const uint32_t xb = (S.ie_xj[k] >> 16) & 0x7fffu;
-          slot = hslot(wq, xb);
-          for (;;) {
-            const uint32_t hw = S.h_w[slot];
-            if (hw == kEmpty) break;
-            if (hw == wq && (S.h_tag[slot] & 0xffffu) == xb) {
-              hit = true;
-              break;
-            }
-            slot = (slot + 1) & (kSlots - 1);
+      const uint32_t t = tt[u], wq = wv[u], x = xx[u], j = xj[u];
+      const bool valid = t < we;
+      if (valid && wq == x) S.ie_e[kk[u]] = bm[u] + t;  // whole-row scan meets x
+      const bool probe = valid && wq > x && (j & 0x80000000u);
+      const uint32_t xb = (j >> 16) & 0x7fffu;
+      bool hit = false, more = false;
+      uint32_t qpos = 0, bkt = 0;
+      if (probe) {
+        bkt = hbucket(wq, xb);
+        const uint4 e = S.hb[bkt];
+        if (e.x == wq && (e.y & 0xffffu) == xb) {
+          hit = true;
+          qpos = e.y >> 16;
+        } else if (e.z == wq && (e.w & 0xffffu) == xb) {
+          hit = true;
+          qpos = e.w >> 16;
+        } else {
+          more = e.z != kEmpty;
+        }
+      }
+      while (__ballot(more)) {  // full bucket: keep probing (rare at load <= 1/2)
+        if (more) {
+          bkt = (bkt + 1) & (kBuckets - 1);
+          const uint4 e = S.hb[bkt];
+          if (e.x == wq && (e.y & 0xffffu) == xb) {
+            hit = true;
+            qpos = e.y >> 16;
+            more = false;
+          } else if (e.z == wq && (e.w & 0xffffu) == xb) {
+            hit = true;
+            qpos = e.w >> 16;
+            more = false;
+          } else {
+            more = e.z != kEmpty;
           }
         }
       }
@@ -340,11 +384,12 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
       if (bal) {
         if (hit)
           q[(qhead + qcnt + __popcll(bal & lanemask_lt())) % kQ] =
-              make_uint2(tt[u], (kk[u] << 16) | slot);
+              make_uint2(t, (kk[u] << 16) | qpos);
         qcnt += __popcll(bal);
         if (qcnt >= (uint32_t)kWave) {
           wave_sync();
-          tri_drain(C, S, q, qhead, kWave);
+          C.n_sel += tri_drain(C.a.del, C.a.thr, C.a.k0, C.a.k1, &S, q, qhead, kWave, C.D0);
+          C.n_tri += 1;
           qhead = (qhead + kWave) % kQ;
           qcnt -= kWave;
         }
@@ -353,7 +398,8 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
   }
   if (qcnt) {
     wave_sync();
-    tri_drain(C, S, q, qhead, qcnt);
+    C.n_sel += tri_drain(C.a.del, C.a.thr, C.a.k0, C.a.k1, &S, q, qhead, qcnt, C.D0);
+    C.n_tri += lane < qcnt ? 1 : 0;
   }
   __syncthreads();
   // ---- finish: eid of every in-edge, (y,x) marks
@@ -368,7 +414,8 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kTB) void k_triangles(TriArgs a, const uint32_t* tlo,
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k_triangles(
+    TriArgs a, const uint32_t* tlo,
                                                    uint64_t ntiles, uint32_t* tile_ctr,
                                                    uint32_t cap) {
   __shared__ TriSmem S;

@@ -14,7 +14,9 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libslim.so")
+# SLIM_LIBRARY may name another build of the same library (e.g. a variant
+# compiled with different launch constants); the default is the in-tree one.
+LIB_PATH = os.environ.get("SLIM_LIBRARY") or os.path.join(_HERE, "libslim.so")
 
 OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, EAGAIN = 0, -1, -2, -3, -4, -5
 VALIDATE = 1
