@@ -315,7 +315,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
   };
   fetch(kcur);
   for (uint32_t wb = ws; wb < we; wb += kWave * kUnroll) {
-    uint32_t kk[kUnroll], bm[kUnroll], xx[kUnroll], xj[kUnroll], wv[kUnroll], tt[kUnroll];
+    uint32_t kk[kUnroll], bm[kUnroll], xx[kUnroll], xj[kUnroll], wv[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const uint32_t base = wb + u * kWave;
@@ -325,58 +325,42 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
         const uint32_t bound = c_nxt;
         ++kcur;
         fetch(kcur);
-        if (t >= bound) {
-          k = kcur;
-          b = c_bmp;
-          x = c_x;
-          j = c_xj;
-        }
+        const bool after = t >= bound;
+        k = after ? kcur : k;
+        b = after ? c_bmp : b;
+        x = after ? c_x : x;
+        j = after ? c_xj : j;
       }
-      tt[u] = t;
+      const bool valid = t < we;
       kk[u] = k;
       bm[u] = b;
-      xx[u] = x;
+      xx[u] = valid ? x : kEmpty;  // no probe and no match past the range
       xj[u] = j;
+      wv[u] = C.a.dag_col[valid ? b + t : 0u];
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
-      wv[u] = tt[u] < we ? C.a.dag_col[bm[u] + tt[u]] : kEmpty;
-#pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const uint32_t t = tt[u], wq = wv[u], x = xx[u], j = xj[u];
-      const bool valid = t < we;
-      if (valid && wq == x) S.ie_e[kk[u]] = bm[u] + t;  // whole-row scan meets x
-      const bool probe = valid && wq > x && (j & 0x80000000u);
+      const uint32_t t = wb + u * kWave + lane, wq = wv[u], x = xx[u], j = xj[u];
+      if (wq == x) S.ie_e[kk[u]] = bm[u] + t;  // whole-row scan meets x
+      const bool probe = (wq > x) & (x != kEmpty) & ((j >> 31) != 0);
       const uint32_t xb = (j >> 16) & 0x7fffu;
-      bool hit = false, more = false;
-      uint32_t qpos = 0, bkt = 0;
-      if (probe) {
-        bkt = hbucket(wq, xb);
-        const uint4 e = S.hb[bkt];
-        if (e.x == wq && (e.y & 0xffffu) == xb) {
-          hit = true;
-          qpos = e.y >> 16;
-        } else if (e.z == wq && (e.w & 0xffffu) == xb) {
-          hit = true;
-          qpos = e.w >> 16;
-        } else {
-          more = e.z != kEmpty;
-        }
-      }
-      while (__ballot(more)) {  // full bucket: keep probing (rare at load <= 1/2)
-        if (more) {
-          bkt = (bkt + 1) & (kBuckets - 1);
-          const uint4 e = S.hb[bkt];
-          if (e.x == wq && (e.y & 0xffffu) == xb) {
-            hit = true;
-            qpos = e.y >> 16;
-            more = false;
-          } else if (e.z == wq && (e.w & 0xffffu) == xb) {
-            hit = true;
-            qpos = e.w >> 16;
-            more = false;
-          } else {
-            more = e.z != kEmpty;
+      uint32_t bkt = hbucket(wq, xb);
+      const uint4 e = S.hb[bkt];
+      const bool m0 = (e.x == wq) & ((e.y & 0xffffu) == xb);
+      const bool m1 = (e.z == wq) & ((e.w & 0xffffu) == xb);
+      bool hit = probe & (m0 | m1);
+      uint32_t qpos = (m0 ? e.y : e.w) >> 16;
+      bool more = probe & !(m0 | m1) & (e.z != kEmpty);
+      if (__ballot(more)) {  // full bucket: keep probing (uncommon)
+        while (__ballot(more)) {
+          if (more) {
+            bkt = (bkt + 1) & (kBuckets - 1);
+            const uint4 f = S.hb[bkt];
+            const bool n0 = (f.x == wq) & ((f.y & 0xffffu) == xb);
+            const bool n1 = (f.z == wq) & ((f.w & 0xffffu) == xb);
+            hit = n0 | n1;
+            qpos = (n0 ? f.y : f.w) >> 16;
+            more = !(n0 | n1) & (f.z != kEmpty);
           }
         }
       }
@@ -475,8 +459,9 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
     __syncthreads();
     const uint32_t r_lo = S.srow[0], r_hi = S.srow[span - 1];
     const uint32_t D0 = a.fstart[r_lo], D1 = a.fstart[r_hi + 1];
-    if (D1 - D0 <= C.cap) {
-      // ---- all rows of the tile share one hash
+    const bool all_rows = D1 - D0 <= C.cap;
+    if (all_rows) {
+      // ---- all rows of the tile share one hash: row start offset per position
       const uint32_t len = D1 - D0;
       for (uint32_t i = tid; i < len; i += kTB) S.u.dpos[i] = 0;
       __syncthreads();
@@ -506,48 +491,73 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
         S.u.dpos[i] = v > cb ? v : cb;
       }
       __syncthreads();
-      C.D0 = D0;
-      tri_build_hash(C, S, len, true);
-      tri_forward_eids(C, S, 0, span, true);
-      for (uint32_t b0 = 0; b0 < nbw; b0 += kBatch)
-        tri_batch(C, S, b0, b0 + kBatch < nbw ? b0 + kBatch : nbw, true);
-      tri_flush_xbits(C, S);
-    } else {
-      // ---- one row at a time, its out-list hashed in passes of C.cap entries
-      uint32_t cur = 0;
-      for (uint32_t r = r_lo; r <= r_hi; ++r) {
-        const int64_t rb = a.row_off[r], re = a.row_off[r + 1];
-        const uint32_t ea = (uint32_t)((rb > j0 ? rb : j0) - j0);
-        const uint32_t eb = (uint32_t)((re < j0 + (int64_t)span ? re : j0 + (int64_t)span) - j0);
-        if (eb <= ea) continue;
-        if (tid == 0) {  // first bw index at or past the end of row r in the tile
-          uint32_t lo = cur, hi = nbw;
-          while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if ((uint32_t)S.bw[mid] < eb)
-              lo = mid + 1;
-            else
-              hi = mid;
+    }
+    // ---- passes: the whole tile (all_rows), or each (row, out-list chunk)
+    // with its in-edges and forward entries; the hashed range is [pD0, pD0+plen)
+    uint32_t r = r_lo, cur = 0, cb = 0, xe = 0, bh = 0, ea = 0, eb = 0;
+    bool row_open = false, done = false;
+    while (!done) {
+      uint32_t pD0, plen, pb0, pb1, pfa, pfb;
+      if (all_rows) {
+        pD0 = D0;
+        plen = D1 - D0;
+        pb0 = 0;
+        pb1 = nbw;
+        pfa = 0;
+        pfb = span;
+        done = true;
+      } else {
+        if (!row_open) {  // find the next row with entries in the tile
+          bool found = false;
+          for (; r <= r_hi; ++r) {
+            const int64_t rb = a.row_off[r], re = a.row_off[r + 1];
+            ea = (uint32_t)((rb > j0 ? rb : j0) - j0);
+            eb = (uint32_t)((re < j0 + (int64_t)span ? re : j0 + (int64_t)span) - j0);
+            if (eb <= ea) continue;
+            if (tid == 0) {  // first bw index at or past the end of row r in the tile
+              uint32_t lo = cur, hi = nbw;
+              while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if ((uint32_t)S.bw[mid] < eb)
+                  lo = mid + 1;
+                else
+                  hi = mid;
+              }
+              S.bcast[2] = lo;
+            }
+            __syncthreads();
+            bh = S.bcast[2];
+            __syncthreads();
+            cb = a.fstart[r];
+            xe = a.fstart[r + 1];
+            if (xe > cb || bh > cur) {
+              found = true;
+              break;
+            }
+            cur = bh;
           }
-          S.bcast[2] = lo;
+          if (!found) break;
+          row_open = true;
         }
-        __syncthreads();
-        const uint32_t bh = S.bcast[2];
-        __syncthreads();
-        const uint32_t xb = a.fstart[r], xe = a.fstart[r + 1];
-        if (xe > xb || bh > cur) {
-          for (uint32_t cb = xb; cb == xb || cb < xe; cb += C.cap) {
-            const uint32_t len = xe - cb < C.cap ? xe - cb : C.cap;
-            C.D0 = cb;
-            tri_build_hash(C, S, len, false);
-            tri_forward_eids(C, S, ea, eb, false);
-            for (uint32_t b0 = cur; b0 < bh; b0 += kBatch)
-              tri_batch(C, S, b0, b0 + kBatch < bh ? b0 + kBatch : bh, false);
-            tri_flush_xbits(C, S);
-          }
+        pD0 = cb;
+        plen = xe - cb < C.cap ? xe - cb : C.cap;
+        pb0 = cur;
+        pb1 = bh;
+        pfa = ea;
+        pfb = eb;
+        cb += C.cap;
+        if (cb >= xe) {  // last chunk of this row
+          row_open = false;
+          cur = bh;
+          ++r;
         }
-        cur = bh;
       }
+      C.D0 = pD0;
+      tri_build_hash(C, S, plen, all_rows);
+      tri_forward_eids(C, S, pfa, pfb, all_rows);
+      for (uint32_t b0 = pb0; b0 < pb1; b0 += kBatch)
+        tri_batch(C, S, b0, b0 + kBatch < pb1 ? b0 + kBatch : pb1, all_rows);
+      tri_flush_xbits(C, S);
     }
   }
   // ---- counters
