@@ -44,8 +44,8 @@ void validate_offsets(const int64_t* row_off, uint64_t n, uint64_t nnz, uint32_t
 void validate_entries(const int64_t* row_off, const uint32_t* col, uint64_t n, uint64_t nnz,
                       uint64_t ntiles, const uint32_t* tile_lo, uint32_t* err, hipStream_t s);
 
-// DAG rows longer than kSortMin are sorted by rank id (slim_sort.hip); the
-// triangle kernel scans shorter rows whole.
+// Every DAG row is sorted by rank id (slim_sort.hip); rows of length up to
+// kSortMin by one thread each.
 constexpr uint32_t kSortMin = 32;
 void sort_rows(const uint2* dag_rng, uint64_t n, uint32_t* dag_col, uint32_t* lists,
                uint32_t* counts, int num_cu, hipStream_t s);

@@ -1,10 +1,11 @@
-// Sorting DAG rows by rank id (rows longer than kSortMin only).
+// Sorting DAG rows by rank id.
 //
 // The triangle kernel finds the in-neighbour edge (y,x) inside out(y) by
 // binary search and scans only the part of out(y) ranked above x, which is
-// the suffix of a sorted row.  Short rows are scanned whole, so they need no
-// sort.  Rows of length kSortMin+1..256 are sorted by one wave each, up to
-// 4096 by one block in LDS, longer rows by one block in global memory.
+// the suffix of a sorted row.  Rows of length 2..kSortMin are sorted by one
+// thread each (insertion sort in a private LDS slice), up to 256 by one
+// wave, up to 4096 by one block in LDS, longer rows by one block in global
+// memory.
 #include "slim_internal.h"
 
 namespace slim {
@@ -25,17 +26,35 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Classify rows: lists[0] gets rows for the wave sort, lists[1] for the block
-// sort, lists[2] for the global sort; counts[0..2] their lengths.
-__global__ void k_sort_classify(const uint2* dag_rng, uint64_t n, uint32_t* wave_list,
-                                uint32_t* block_list, uint32_t* huge_list, uint32_t* counts) {
+// Sort short rows in place (one thread each) and classify the others:
+// wave_list gets rows for the wave sort, block_list for the block sort,
+// huge_list for the global sort; counts[0..2] their lengths.
+__global__ __launch_bounds__(kBlock) void k_sort_classify(const uint2* dag_rng, uint64_t n,
+                                                          uint32_t* dag_col, uint32_t* wave_list,
+                                                          uint32_t* block_list,
+                                                          uint32_t* huge_list, uint32_t* counts) {
+  __shared__ uint32_t slice[kBlock * (kSortMin + 1)];  // stride kSortMin+1: no bank conflicts
+  uint32_t* my = slice + threadIdx.x * (kSortMin + 1);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
     const uint64_t x = base + threadIdx.x;
-    uint32_t len = 0;
+    uint32_t len = 0, beg = 0;
     if (x < n) {
       const uint2 r = dag_rng[x];
       len = r.y - r.x;
+      beg = r.x;
+    }
+    if (len >= 2 && len <= kSortMin) {
+      for (uint32_t i = 0; i < len; ++i) {
+        const uint32_t v = dag_col[beg + i];
+        uint32_t k = i;
+        while (k > 0 && my[k - 1] > v) {
+          my[k] = my[k - 1];
+          --k;
+        }
+        my[k] = v;
+      }
+      for (uint32_t i = 0; i < len; ++i) dag_col[beg + i] = my[i];
     }
     const bool cls[3] = {len > kSortMin && len <= kWaveSortMax,
                          len > kWaveSortMax && len <= kBlockSortMax, len > kBlockSortMax};
@@ -160,8 +179,8 @@ void sort_rows(const uint2* dag_rng, uint64_t n, uint32_t* dag_col, uint32_t* li
   unsigned g = (unsigned)((n + kBlock - 1) / kBlock);
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_sort_classify, dim3(g), dim3(kBlock), 0, s, dag_rng, n, wave_list,
-                     block_list, huge_list, counts);
+  hipLaunchKernelGGL(k_sort_classify, dim3(g), dim3(kBlock), 0, s, dag_rng, n, dag_col,
+                     wave_list, block_list, huge_list, counts);
   hipLaunchKernelGGL(k_sort_wave, dim3(num_cu * 8), dim3(kBlock), 0, s, dag_rng, dag_col,
                      wave_list, counts + 0);
   hipLaunchKernelGGL(k_sort_block, dim3(num_cu * 4), dim3(kBlock), 0, s, dag_rng, dag_col,

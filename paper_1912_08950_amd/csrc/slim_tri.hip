@@ -51,7 +51,7 @@ struct TriSmem {
   uint4 ie[kBatch];           // {scan begin, x rank, y old id, x old id}
   uint32_t ie_pre[kBatch + 1];
   uint32_t ie_e[kBatch];      // DAG position of (y,x) (kEmpty until found)
-  uint32_t ie_xj[kBatch];     // (out(x) nonempty << 31) | (row start offset << 16) | CSR index
+  uint4 ie_scan[kBatch];      // {scan begin - item base, hash tag, next in-edge start, 0}
   uint32_t ie_flag[(kBatch + 31) / 32];
   union {
     uint32_t dpos[kHashCap];  // row start offset of each hashed position
@@ -234,11 +234,13 @@ __device__ __forceinline__ uint32_t tri_drain(uint32_t* del, uint64_t thr, uint3
 
 // Process the in-edges bw[b0, b1) of the tile against the current hash.
 __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool all_rows) {
-  const int tid = threadIdx.x, w = tid / kWave;
+  const int tid = threadIdx.x;
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const uint32_t lane = lane_id();
   const uint32_t nin = b1 - b0;
-  // ---- setup: one thread per in-edge
-  uint32_t cnt = 0;
+  // ---- setup: one thread per in-edge (y,x); x is found in sorted out(y) by
+  // binary search, and the items are the entries of out(y) after it
+  uint32_t cnt = 0, bmp = 0, xtag = 0;
   if ((uint32_t)tid < nin) {
     const uint32_t i = S.bw[b0 + tid];
     const uint64_t j = (uint64_t)C.j0 + i;
@@ -248,43 +250,42 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     const uint32_t x = C.a.rank[r];
     const uint2 yr = C.a.dag_rng[y];
     const uint32_t fs = C.a.fstart[r], fe = C.a.fstart[r + 1];
-    uint32_t beg = yr.x, e = kEmpty;
-    if (yr.y - yr.x > kSortMin) {  // sorted row: x by binary search
-      uint32_t lo = yr.x, hi = yr.y;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (C.a.dag_col[mid] < x)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      e = lo;
-      beg = lo + 1;
-      if (fe == fs) beg = yr.y;  // out(x) empty: no triangle, nothing to scan
+    uint32_t lo = yr.x, hi = yr.y;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (C.a.dag_col[mid] < x)
+        lo = mid + 1;
+      else
+        hi = mid;
     }
+    const uint32_t e = lo;  // dag_col[e] == x
+    const uint32_t beg = fe > fs ? e + 1 : yr.y;  // out(x) empty: no triangle, no scan
     cnt = yr.y - beg;
-    // An empty out(x) starts where the next row starts, so its row offset is
-    // not a unique tag: in-edges into it must not probe at all.
-    const uint32_t xb = all_rows ? (fs - C.D0) : 0u;
+    xtag = all_rows ? (fs - C.D0) : 0u;
     S.ie[tid] = make_uint4(beg, x, c, r);
     S.ie_e[tid] = e;
-    S.ie_xj[tid] = (fe > fs ? 0x80000000u : 0u) | (xb << 16) | i;
+    C.a.eid[j] = e;
+    bmp = beg;
   }
   if ((uint32_t)tid < (kBatch + 31) / 32) S.ie_flag[tid] = 0;
-  {  // block exclusive scan of cnt into ie_pre
+  {  // block exclusive scan of cnt into ie_pre; scan records {beg - pre, tag, next start}
     const uint64_t incl = wave_incl_sum64(cnt);
     if (lane == kWave - 1) S.wsum[w] = (uint32_t)incl;
     __syncthreads();
     uint32_t before = 0, all = 0;
     for (int i = 0; i < kTW; ++i) {
-      if (i < w) before += S.wsum[i];
+      if ((uint32_t)i < w) before += S.wsum[i];
       all += S.wsum[i];
     }
-    if ((uint32_t)tid < nin) S.ie_pre[tid] = before + (uint32_t)incl - cnt;
+    const uint32_t pre = before + (uint32_t)incl - cnt;
+    if ((uint32_t)tid < nin) {
+      S.ie_pre[tid] = pre;
+      S.ie_scan[tid] = make_uint4(bmp - pre, xtag, pre + cnt, 0u);
+    }
     if (tid == 0) S.ie_pre[nin] = all;
     __syncthreads();
   }
-  const uint32_t W = S.ie_pre[nin];
+  const uint32_t W = __builtin_amdgcn_readfirstlane(S.ie_pre[nin]);
   // ---- items: wave w takes the contiguous range [ws, we).  The current
   // in-edge's fields stay in scalar registers; a window of 64 items crosses
   // an in-edge boundary only now and then (a short scalar loop).
@@ -305,59 +306,53 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     kcur = lo;
   }
   kcur = __builtin_amdgcn_readfirstlane(kcur);
-  uint32_t c_bmp, c_x, c_xj, c_nxt;  // scan begin - item base, x rank, tag word, next start
+  uint32_t c_bmp, c_tag, c_nxt;  // scan begin - item base, hash tag, next in-edge start
   auto fetch = [&](uint32_t k) {
-    const uint4 ie = S.ie[k];
-    c_bmp = __builtin_amdgcn_readfirstlane(ie.x - S.ie_pre[k]);
-    c_x = __builtin_amdgcn_readfirstlane(ie.y);
-    c_xj = __builtin_amdgcn_readfirstlane(S.ie_xj[k]);
-    c_nxt = __builtin_amdgcn_readfirstlane(S.ie_pre[k + 1]);
+    const uint4 r = S.ie_scan[k];
+    c_bmp = __builtin_amdgcn_readfirstlane(r.x);
+    c_tag = __builtin_amdgcn_readfirstlane(r.y);
+    c_nxt = __builtin_amdgcn_readfirstlane(r.z);
   };
   fetch(kcur);
   for (uint32_t wb = ws; wb < we; wb += kWave * kUnroll) {
-    uint32_t kk[kUnroll], bm[kUnroll], xx[kUnroll], xj[kUnroll], wv[kUnroll];
+    uint32_t kk[kUnroll], xb[kUnroll], wv[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const uint32_t base = wb + u * kWave;
       const uint32_t t = base + lane;
-      uint32_t k = kcur, b = c_bmp, x = c_x, j = c_xj;
-      while (c_nxt < base + kWave && c_nxt < we) {  // in-edge boundaries in this window
+      uint32_t k = kcur, b = c_bmp, g = c_tag;
+      const uint32_t lim = base + kWave < we ? base + kWave : we;
+      while (c_nxt < lim) {  // the next in-edge starts inside this window
         const uint32_t bound = c_nxt;
         ++kcur;
         fetch(kcur);
         const bool after = t >= bound;
         k = after ? kcur : k;
         b = after ? c_bmp : b;
-        x = after ? c_x : x;
-        j = after ? c_xj : j;
+        g = after ? c_tag : g;
       }
-      const bool valid = t < we;
-      kk[u] = k;
-      bm[u] = b;
-      xx[u] = valid ? x : kEmpty;  // no probe and no match past the range
-      xj[u] = j;
-      wv[u] = C.a.dag_col[valid ? b + t : 0u];
+      kk[u] = t < we ? k : 0xffffu;  // 0xffff: lane past the range
+      xb[u] = g;
+      wv[u] = C.a.dag_col[t < we ? b + t : 0u];
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const uint32_t t = wb + u * kWave + lane, wq = wv[u], x = xx[u], j = xj[u];
-      if (wq == x) S.ie_e[kk[u]] = bm[u] + t;  // whole-row scan meets x
-      const bool probe = (wq > x) & (x != kEmpty) & ((j >> 31) != 0);
-      const uint32_t xb = (j >> 16) & 0x7fffu;
-      uint32_t bkt = hbucket(wq, xb);
+      const uint32_t t = wb + u * kWave + lane, wq = wv[u], g = xb[u];
+      const bool valid = kk[u] != 0xffffu;
+      uint32_t bkt = hbucket(wq, g);
       const uint4 e = S.hb[bkt];
-      const bool m0 = (e.x == wq) & ((e.y & 0xffffu) == xb);
-      const bool m1 = (e.z == wq) & ((e.w & 0xffffu) == xb);
-      bool hit = probe & (m0 | m1);
+      const bool m0 = (e.x == wq) & ((e.y & 0xffffu) == g);
+      const bool m1 = (e.z == wq) & ((e.w & 0xffffu) == g);
+      bool hit = valid & (m0 | m1);
       uint32_t qpos = (m0 ? e.y : e.w) >> 16;
-      bool more = probe & !(m0 | m1) & (e.z != kEmpty);
+      bool more = valid & !(m0 | m1) & (e.z != kEmpty);
       if (__ballot(more)) {  // full bucket: keep probing (uncommon)
         while (__ballot(more)) {
           if (more) {
             bkt = (bkt + 1) & (kBuckets - 1);
             const uint4 f = S.hb[bkt];
-            const bool n0 = (f.x == wq) & ((f.y & 0xffffu) == xb);
-            const bool n1 = (f.z == wq) & ((f.w & 0xffffu) == xb);
+            const bool n0 = (f.x == wq) & ((f.y & 0xffffu) == g);
+            const bool n1 = (f.z == wq) & ((f.w & 0xffffu) == g);
             hit = n0 | n1;
             qpos = (n0 ? f.y : f.w) >> 16;
             more = !(n0 | n1) & (f.z != kEmpty);
@@ -386,15 +381,9 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     C.n_tri += lane < qcnt ? 1 : 0;
   }
   __syncthreads();
-  // ---- finish: eid of every in-edge, (y,x) marks
-  if ((uint32_t)tid < nin) {
-    const uint32_t e = S.ie_e[tid];
-    const uint32_t i = S.ie_xj[tid] & 0xffffu;
-    if (e != kEmpty) {
-      C.a.eid[(uint64_t)C.j0 + i] = e;
-      if (S.ie_flag[tid >> 5] & (1u << (tid & 31))) bit_set(C.a.del, e);
-    }
-  }
+  // ---- finish: (y,x) marks
+  if ((uint32_t)tid < nin && (S.ie_flag[tid >> 5] & (1u << (tid & 31))))
+    bit_set(C.a.del, S.ie_e[tid]);
   __syncthreads();
 }
 

@@ -236,3 +236,26 @@ def test_rmat20_tr_full(slim, rmat20, p):
 def test_rmat20_es_full(slim, rmat20):
     assert_same(gpu_run(slim, rmat20, "es", 0.5, 1, validate=False),
                 oracle_run(rmat20, "es", 0.5, 1))
+
+
+@pytest.fixture(scope="module")
+def rmat24():
+    return gg.rmat(24, 16, 1)
+
+
+def test_rmat24_tr_full(slim, rmat24):
+    """R-MAT scale 24 (edge factor 16, ~0.5B CSR entries), p = 0.5, the
+    benchmark workload in the benchmark's launch configuration: the whole
+    output against the oracle's stored digest, and sampled rows recomputed
+    by the per-row oracle."""
+    ro, col, st = _check_digest(slim, rmat24, "rmat24_tr_p0.5")
+    rng = np.random.default_rng(11)
+    deg = rmat24.degrees()
+    rows = np.concatenate([rng.choice(np.flatnonzero((deg > 0) & (deg < 200)), 200, replace=False),
+                           rng.choice(np.flatnonzero((deg >= 200) & (deg < 2000)), 10,
+                                      replace=False)])
+    _check_sampled_rows(rmat24, ro, col, 0.5, 1, rows)
+
+
+def test_rmat24_es_full(slim, rmat24):
+    _check_digest(slim, rmat24, "rmat24_es_p0.5")
