@@ -335,27 +335,39 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
       xb[u] = g;
       wv[u] = C.a.dag_col[t < we ? b + t : 0u];
     }
+    // Probe: the home bucket and the next one (four slots, read together for
+    // all windows); a key can only sit further on if both are full.
+    uint4 e0[kUnroll], e1[kUnroll];
+    uint32_t bk[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      bk[u] = hbucket(wv[u], xb[u]);
+      e0[u] = S.hb[bk[u]];
+      e1[u] = S.hb[(bk[u] + 1) & (kBuckets - 1)];
+    }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const uint32_t t = wb + u * kWave + lane, wq = wv[u], g = xb[u];
       const bool valid = kk[u] != 0xffffu;
-      uint32_t bkt = hbucket(wq, g);
-      const uint4 e = S.hb[bkt];
+      const uint4 e = e0[u], f = e1[u];
       const bool m0 = (e.x == wq) & ((e.y & 0xffffu) == g);
       const bool m1 = (e.z == wq) & ((e.w & 0xffffu) == g);
-      bool hit = valid & (m0 | m1);
-      uint32_t qpos = (m0 ? e.y : e.w) >> 16;
-      bool more = valid & !(m0 | m1) & (e.z != kEmpty);
-      if (__ballot(more)) {  // full bucket: keep probing (uncommon)
+      const bool m2 = (f.x == wq) & ((f.y & 0xffffu) == g);
+      const bool m3 = (f.z == wq) & ((f.w & 0xffffu) == g);
+      bool hit = valid & (m0 | m1 | m2 | m3);
+      uint32_t qpos = (m0 ? e.y : m1 ? e.w : m2 ? f.y : f.w) >> 16;
+      bool more = valid & !(m0 | m1 | m2 | m3) & (e.z != kEmpty) & (f.z != kEmpty);
+      uint32_t bkt = (bk[u] + 1) & (kBuckets - 1);
+      if (__ballot(more)) {  // both buckets full: keep probing (rare)
         while (__ballot(more)) {
           if (more) {
             bkt = (bkt + 1) & (kBuckets - 1);
-            const uint4 f = S.hb[bkt];
-            const bool n0 = (f.x == wq) & ((f.y & 0xffffu) == g);
-            const bool n1 = (f.z == wq) & ((f.w & 0xffffu) == g);
+            const uint4 h = S.hb[bkt];
+            const bool n0 = (h.x == wq) & ((h.y & 0xffffu) == g);
+            const bool n1 = (h.z == wq) & ((h.w & 0xffffu) == g);
             hit = n0 | n1;
-            qpos = (n0 ? f.y : f.w) >> 16;
-            more = !(n0 | n1) & (f.z != kEmpty);
+            qpos = (n0 ? h.y : h.w) >> 16;
+            more = !(n0 | n1) & (h.z != kEmpty);
           }
         }
       }
