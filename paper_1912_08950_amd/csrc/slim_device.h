@@ -55,14 +55,13 @@ __device__ __forceinline__ void philox_w01(uint32_t x0, uint32_t x1, uint32_t x2
                                            uint32_t& w1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t a_hi = __umulhi(0xD2511F53u, x0);
-    const uint32_t a_lo = 0xD2511F53u * x0;
-    const uint32_t b_hi = __umulhi(0xCD9E8D57u, x2);
-    const uint32_t b_lo = 0xCD9E8D57u * x2;
-    x0 = b_hi ^ x1 ^ k0;
-    x1 = b_lo;
-    x2 = a_hi ^ x3 ^ k1;
-    x3 = a_lo;
+    // one 32x32->64 product each (a single multiply-add instruction on gfx950)
+    const uint64_t a = (uint64_t)0xD2511F53u * x0;
+    const uint64_t b = (uint64_t)0xCD9E8D57u * x2;
+    x0 = (uint32_t)(b >> 32) ^ x1 ^ k0;
+    x1 = (uint32_t)b;
+    x2 = (uint32_t)(a >> 32) ^ x3 ^ k1;
+    x3 = (uint32_t)a;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }

@@ -24,7 +24,7 @@ namespace slim {
 
 constexpr int kTB = 512;             // threads per block
 constexpr int kTW = kTB / kWave;     // waves per block
-constexpr int kTT = 2048;            // CSR entries per tile
+constexpr int kTT = 1024;            // CSR entries per tile
 constexpr int kTC = kTT / kWave;     // 64-entry chunks per tile
 constexpr int kHashCap = 2048;       // out-list entries hashed per pass
 constexpr int kBuckets = 2048;       // hash buckets of two slots (load <= 1/2)
@@ -224,8 +224,8 @@ __device__ __forceinline__ uint32_t tri_drain(uint32_t* del, uint64_t thr, uint3
       } else if (excl == c) {  // edge {x,w}: position qpos of the hashed range
         const uint32_t bit = D0 % 32 + qpos;
         atomicOr(&S.xbits[bit >> 5], 1u << (bit & 31));
-      } else {  // edge {y,w}: global bitmap
-        if (!bit_get(del, p_yw)) bit_set(del, p_yw);
+      } else {  // edge {y,w}: global bitmap (no return value: nothing waits on it)
+        bit_set(del, p_yw);
       }
     }
   }
