@@ -22,13 +22,58 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
+def kernel_source_hash():
+    """Digest of the HIP sources, to tell whether stored counters still apply."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1912_08950_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(path):
+    """HBM bytes per launch of the triangle kernel from a committed rocprofv3
+    summary ("hbm_bytes_per_launch:" line), if it was taken on the current
+    kernel sources ("kernel_source_sha256:" line); else None."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith((" ", "#", "|")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain device copy of known size (1 GiB, 5 launches) so that the
+    FETCH_SIZE / WRITE_SIZE counters can be scaled to bytes."""
+    import torch
+    n = 1 << 28  # int32 elements = 1 GiB
+    src = torch.arange(n, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 5}), flush=True)
+
+
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def dag_work(g):
-    """Per-graph work units of the triangle kernel from the degree-ordered
-    DAG: out-degrees, sum out^2 (scan volume) and sum C(out,2)."""
+    """Work units of the degree-ordered DAG: S = sum_v in(v)*out(v) (the
+    wedge count of the (degree, id) orientation), sum out^2 and
+    sum C(out,2) (the scan items of the middle-vertex kernel)."""
     import numpy as np
     deg = np.diff(g.row_off)
     order = np.lexsort((np.arange(g.n), deg))  # rank order = (degree, id)
@@ -37,19 +82,26 @@ def dag_work(g):
     rows = np.repeat(np.arange(g.n, dtype=np.int64), deg)
     fwd = rank[g.col.astype(np.int64)] > rank[rows]
     outdeg = np.bincount(rows[fwd], minlength=g.n).astype(np.float64)
-    return {"m": g.m, "sum_out_sq": float(np.sum(outdeg**2)),
+    indeg = deg.astype(np.float64) - outdeg
+    return {"m": g.m, "S": float(np.sum(indeg * outdeg)), "sum_out_sq": float(np.sum(outdeg**2)),
             "sum_out_pairs": float(np.sum(outdeg * (outdeg - 1) / 2)),
             "max_out": int(outdeg.max()) if g.n else 0}
 
 
 def tri_kernel_bytes(g, work):
-    """Algorithmic bytes of one launch of the triangle kernel:
-    CSR rows of every vertex (4 B/entry + 16 B/vertex of offsets and ranges),
-    rank gathers (4 B/entry), out(x) staged once (4 B/DAG edge), out(y)
-    scanned once per in-edge (4 B x sum_y out(y)^2), backward eid writes
-    (4 B/edge), and the deletion bitmap (m/8 B)."""
-    return (4 * g.nnz + 16 * g.n + 4 * g.nnz + 4 * g.m + 4 * work["sum_out_sq"] + 4 * g.m
-            + g.m / 8)
+    """Algorithmic bytes of one launch of the triangle kernel, per the
+    hot-path byte model of the design: each out-list staged once (4 B per
+    DAG edge), one out-list streamed per DAG edge (4 B x S with
+    S = sum_v in(v) out(v)), and the deletion bitmap (m/8 B)."""
+    return 4 * g.m + 4 * work["S"] + g.m / 8
+
+
+def step_bytes(g, work, m_out):
+    """Algorithmic bytes of one whole step (all phases) under the same model:
+    read the CSR, write and read the DAG, stream S, compact, bitmap."""
+    n1 = g.n + 1
+    return (4 * g.nnz + 8 * n1) + (4 * g.m + 8 * n1) + (4 * g.m + 4 * work["S"]) \
+        + (4 * g.nnz + 8 * m_out + 8 * n1) + g.m / 8
 
 
 def cpu_baseline(scale):
@@ -78,7 +130,12 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-scale", type=int, default=18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(graphs are processed whole on one device); run with --gpus 1", file=sys.stderr)
@@ -137,6 +194,7 @@ def main():
     tri_ms = float(np.mean(phases["triangles"]))
     tri_bytes = tri_kernel_bytes(g, work)
     achieved = tri_bytes / (tri_ms * 1e-3) / 1e9
+    traffic = stored_traffic(os.path.join(ROOT, "profiles", f"k_triangles_rmat{args.scale}.txt"))
     result = {
         "metric": "input edges/s for Triangle p-1-Reduction (R-MAT s24); batched vs plain; p99 ms",
         "value": g.m / (ms_per_step * 1e-3),
@@ -162,7 +220,10 @@ def main():
         "edge_sample": {"ms": es_ms, "edges_per_s": g.m / (es_ms * 1e-3)},
         "roofline": {"kernel": "k_triangles", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes": tri_bytes, "kernel_ms": tri_ms},
+                     "traffic": traffic, "algorithmic_bytes": tri_bytes, "kernel_ms": tri_ms,
+                     "scan_items": work["sum_out_pairs"],
+                     "scan_bytes_per_s": 4 * work["sum_out_pairs"] / (tri_ms * 1e-3)},
+        "step_algorithmic_gbs": step_bytes(g, work, stats["m_out"]) / (ms_per_step * 1e-3) / 1e9,
     }
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on R-MAT scale {args.cpu_scale}")
