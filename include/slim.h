@@ -11,7 +11,9 @@
  *     is in slim_last_error() (thread-local, valid until the next call on
  *     the same thread).  No C++ exception crosses this interface.
  *   - "d_" pointers are device (HBM) pointers owned by the caller; the
- *     library never allocates device memory and never frees caller memory.
+ *     library never frees caller memory.  Compute calls allocate no device
+ *     memory: their scratch is a caller workspace.  (A batch holds a HIP
+ *     graph and a small pinned host buffer of its own.)
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Compute calls only enqueue work on it and return; outputs and stats
  *     are valid once the stream has been synchronised.  Calls on one stream
@@ -132,12 +134,87 @@ SLIM_API int slim_edge_sample(const slim_graph_t* g, double p, uint64_t seed, vo
                      uint64_t ws_bytes, int64_t* d_out_row_off, uint32_t* d_out_col,
                      slim_stats_t* d_stats, void* stream);
 
+/* ------------------------------------------------------------ batches
+ * Many graphs in one launch sequence: the graphs are gathered into one
+ * union CSR in the workspace (graph g's vertex and entry ranges follow
+ * graph g-1's), every phase runs once over the union with work tiles that
+ * never straddle two graphs, and each graph's output is written to its own
+ * arrays.  A batch job computes exactly what the single-graph call with the
+ * same (graph, op, p, seed) computes, bit for bit; jobs of one batch may
+ * mix TR and ES and differ in p and seed.  The paper runs its kernels as
+ * independent concurrent instances (section 4.5, runtime listing
+ * `lst:general`, `run_kernels`); batching
+ * many graphs into one device pass is this library's systems extension.
+ *
+ * The first slim_batch_run captures the launch sequence into a HIP graph;
+ * later runs with the same workspace and knobs replay it as one graph
+ * launch (per-graph output pointers live in a device table that a run
+ * refreshes with one host-to-device copy when they change).
+ */
+typedef struct slim_job_params {
+  int32_t op;    /* SLIM_OP_TR or SLIM_OP_ES */
+  int32_t pad;   /* must be 0 */
+  double p;      /* as slim_triangle_reduce / slim_edge_sample */
+  uint64_t seed; /* as slim_triangle_reduce / slim_edge_sample */
+} slim_job_params_t;
+
+typedef struct slim_out {
+  int64_t* row_off;    /* device int64[n+1] */
+  uint32_t* col;       /* device uint32[nnz] capacity (may be NULL if nnz = 0) */
+  slim_stats_t* stats; /* optional device stats */
+} slim_out_t;
+
+typedef struct slim_batch slim_batch_t; /* opaque, library-owned */
+
+/*
+ * Build a batch over `count` >= 1 loaded graphs (all on the current
+ * device; handles and their arrays must outlive the batch) with one job
+ * each.  The union must satisfy the single-graph limits: sum of n <= 2^32-1
+ * and sum of m <= 2^32-1.  Errors: SLIM_EINVAL (NULL, bad op/p, limits,
+ * graphs on another device), SLIM_EDEVICE.
+ */
+SLIM_API int slim_batch_create(const slim_graph_t* const* graphs, const slim_job_params_t* jobs,
+                               uint32_t count, slim_batch_t** out);
+/* Device workspace (bytes) of slim_batch_run, independent of the knobs. */
+SLIM_API int slim_batch_workspace_size(const slim_batch_t* b, uint64_t* bytes);
+/*
+ * Run every job of the batch on `stream`.  outs[g] receives graph g's
+ * result (out arrays as in slim_triangle_reduce).  d_ws: at least
+ * slim_batch_workspace_size bytes, 256-byte aligned.  Runs that share a
+ * batch or a workspace must not overlap.  Errors: SLIM_EINVAL, SLIM_ENOMEM
+ * (workspace too small), SLIM_EDEVICE.
+ */
+SLIM_API int slim_batch_run(slim_batch_t* b, void* d_ws, uint64_t ws_bytes, const slim_out_t* outs,
+                            void* stream);
+/*
+ * Scheduling knobs of one batch (same keys as slim_tune_set, plus
+ * "use_graph" 0/1: replay a captured HIP graph, default 1).  Results never
+ * depend on them.
+ */
+SLIM_API int slim_batch_set(slim_batch_t* b, const char* key, int64_t value);
+SLIM_API int slim_batch_get(const slim_batch_t* b, const char* key, int64_t* value);
+/*
+ * Autotuner: picks the batch's triangle tile size, blocks per CU and hash
+ * chunk by timing real runs (coordinate descent over the candidates, each
+ * timed with HIP events as the best of two replays), then keeps the best.
+ * With a non-NULL `cache_path` the choice is looked up first under a key of
+ * (device, CU count, batch size, union size) and, if absent, appended to
+ * that text file after tuning.  Runs the batch several times: outs hold a
+ * valid result afterwards.  Synchronises `stream`.
+ */
+SLIM_API int slim_batch_tune(slim_batch_t* b, void* d_ws, uint64_t ws_bytes, const slim_out_t* outs,
+                             const char* cache_path, void* stream);
+/* Release a batch (NULL is ignored).  The caller synchronises the streams
+ * of its runs first. */
+SLIM_API void slim_batch_free(slim_batch_t* b);
+
 /* ------------------------------------------------- scheduling knobs
  * Process-wide settings that change launch shapes and the split of work
  * only: results are bit-identical under every setting (the test suite runs
  * the parity checks under several).  Keys:
  *   "tri_chunk"          out(x) entries hashed in LDS per pass, 32..2048
  *   "tri_blocks_per_cu"  resident blocks per CU of the triangle kernel, 1..64
+ *   "tri_tile"           CSR entries per triangle work tile: 256, 512 or 1024
  * Unknown key or value out of range -> SLIM_EINVAL.
  */
 SLIM_API int slim_tune_set(const char* key, int64_t value);

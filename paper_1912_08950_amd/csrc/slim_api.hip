@@ -1,27 +1,27 @@
 // C ABI of libslim (declared in include/slim.h): argument checks, workspace
-// carving and the launch sequence of each operation on the caller's stream.
+// carving and the launch sequence of a graph set on the caller's stream --
+// one graph for slim_triangle_reduce / slim_edge_sample, many for a batch
+// (gathered into a union CSR, captured once into a HIP graph and replayed).
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
+#include "slim_batch.h"
 #include "slim_internal.h"
 
-struct slim_graph {
-  const int64_t* row_off;
-  const uint32_t* col;
-  uint64_t n;
-  uint64_t nnz;
-  int device;
-  int num_cu;
-};
+namespace slim {
 
 namespace {
-
 thread_local std::string g_err;
+}
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -44,6 +44,10 @@ int hip_check(const char* what) {
   return ok();
 }
 
+const char* last_error() { return g_err.c_str(); }
+
+namespace {
+
 constexpr uint64_t kAlign = 256;
 
 struct Carve {
@@ -59,82 +63,16 @@ struct Carve {
 
 uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
-struct Common {
-  uint64_t ntiles;
-  uint64_t tile_lo, tile_cnt, tile_base, scan_tmp;
-};
-
-struct TrLayout : Common {
-  uint64_t ka, va, kb, vb, rank, hist, hist_scan;
-  uint64_t fstart, dag_rng, dag_col, eid, del, counters;
-  uint64_t sort_lists, sort_counts, tri_tlo, tri_ctr;
-  uint64_t total;
-  int passes;
-};
-
-struct EsLayout : Common {
-  uint64_t total;
-};
-
-int radix_passes(uint64_t n, uint64_t nnz) {
-  uint64_t maxdeg = n > 0 ? n - 1 : 0;
-  if (nnz < maxdeg) maxdeg = nnz;
-  int bits = 0;
-  while (bits < 64 && (maxdeg >> bits) != 0) ++bits;
-  int passes = (bits + 7) / 8;
-  return passes < 1 ? 1 : passes;
-}
-
-TrLayout tr_layout(uint64_t n, uint64_t nnz) {
-  TrLayout L{};
-  Carve c;
-  const uint64_t m = nnz / 2;
-  L.ntiles = ceil_div(nnz, slim::kTile);
-  L.passes = radix_passes(n, nnz);
-  const uint64_t hist = slim::sort_hist_elems(n);
-  uint64_t st = slim::scan_tmp_elems(hist);
-  uint64_t st2 = slim::scan_tmp_elems(L.ntiles);
-  if (st2 > st) st = st2;
-  L.ka = c.take<uint32_t>(n);
-  L.va = c.take<uint32_t>(n);
-  L.kb = c.take<uint32_t>(n);
-  L.vb = c.take<uint32_t>(n);
-  L.rank = c.take<uint32_t>(n);
-  L.hist = c.take<uint32_t>(hist);
-  L.hist_scan = c.take<uint64_t>(hist + 1);
-  L.scan_tmp = c.take<uint64_t>(st + 1);
-  L.tile_lo = c.take<uint32_t>(L.ntiles + 1);
-  L.tile_cnt = c.take<uint32_t>(L.ntiles + 1);
-  L.tile_base = c.take<uint64_t>(L.ntiles + 1);
-  L.fstart = c.take<uint32_t>(n + 1);
-  L.dag_rng = c.take<uint2>(n);
-  L.dag_col = c.take<uint32_t>(m);
-  L.eid = c.take<uint32_t>(nnz);
-  L.del = c.take<uint32_t>(ceil_div(m, 32) + 1);
-  L.counters = c.take<uint64_t>(4);
-  L.sort_lists = c.take<uint32_t>(3 * n);
-  L.sort_counts = c.take<uint32_t>(4);
-  L.tri_tlo = c.take<uint32_t>(slim::tri_tiles(nnz) + 1);
-  L.tri_ctr = c.take<uint32_t>(4);
-  L.total = c.off;
-  return L;
-}
-
-EsLayout es_layout(uint64_t nnz) {
-  EsLayout L{};
-  Carve c;
-  L.ntiles = ceil_div(nnz, slim::kTile);
-  L.scan_tmp = c.take<uint64_t>(slim::scan_tmp_elems(L.ntiles) + 1);
-  L.tile_lo = c.take<uint32_t>(L.ntiles + 1);
-  L.tile_cnt = c.take<uint32_t>(L.ntiles + 1);
-  L.tile_base = c.take<uint64_t>(L.ntiles + 1);
-  L.total = c.off;
-  return L;
-}
-
 template <class T>
 T* at(void* base, uint64_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+}  // namespace
+
+uint64_t threshold(double p) {
+  if (p >= 1.0) return uint64_t(1) << 32;
+  return (uint64_t)std::floor(p * 4294967296.0);
 }
 
 int check_p(double p) {
@@ -142,11 +80,103 @@ int check_p(double p) {
   return SLIM_OK;
 }
 
-uint64_t threshold(double p) {
-  if (p >= 1.0) return uint64_t(1) << 32;
-  return (uint64_t)std::floor(p * 4294967296.0);
+// 8-bit radix passes that order degrees up to maxdeg.
+int radix_passes(uint64_t maxdeg) {
+  int bits = 0;
+  while (bits < 64 && (maxdeg >> bits) != 0) ++bits;
+  int passes = (bits + 7) / 8;
+  return passes < 1 ? 1 : passes;
 }
 
+uint64_t tiles_of(uint64_t ne, uint64_t tile) {
+  const uint64_t t = ceil_div(ne, tile);
+  return t < 1 ? 1 : t;
+}
+
+SetShape single_shape(uint64_t n, uint64_t nnz, bool tr) {
+  SetShape S;
+  S.count = 1;
+  S.N = n;
+  S.NNZ = nnz;
+  S.gathered = false;
+  S.has_tr = tr;
+  S.n_c = tiles_of(nnz, kTile);
+  S.n_u = S.n_c;
+  for (int i = 0; i < 3; ++i) S.n_tri[i] = tiles_of(nnz, kTriTileMin << i);
+  S.nvt = S.net = 0;
+  uint64_t maxdeg = n > 0 ? n - 1 : 0;
+  if (nnz < maxdeg) maxdeg = nnz;
+  S.passes = radix_passes(maxdeg);
+  return S;
+}
+
+SetLayout set_layout(const SetShape& S) {
+  SetLayout L{};
+  // header, packed: gd[count+1] (the last is the union), t0c, t0t [count+1],
+  // t0u[2], vt0, et0 [count+1]; a one-graph set's first four fit 256 bytes
+  const uint64_t cnt1 = (uint64_t)S.count + 1;
+  L.gd = 0;
+  L.t0c = L.gd + sizeof(GDesc) * cnt1;
+  L.t0t = L.t0c + 8 * cnt1;
+  L.t0u = L.t0t + 8 * cnt1;
+  L.vt0 = L.t0u + 16;
+  L.et0 = L.vt0 + 8 * cnt1;
+  L.hdr_bytes = L.et0 + 8 * cnt1;
+  Carve c;
+  c.off = (L.hdr_bytes + kAlign - 1) / kAlign * kAlign;
+  if (S.gathered) {
+    L.urow = c.take<int64_t>(S.N + 1);
+    L.ucol = c.take<uint32_t>(S.NNZ);
+  }
+  L.recs_c = c.take<TileRec>(S.n_c);
+  const uint64_t nt = std::max(S.n_c, S.n_u);
+  L.tile_cnt = c.take<uint32_t>(nt + 1);
+  L.tile_base = c.take<uint64_t>(nt + 1);
+  uint64_t st = scan_tmp_elems(nt);
+  if (S.has_tr) {
+    const uint64_t n = S.N, m = S.NNZ / 2;
+    const uint64_t hist = sort_hist_elems(n);
+    st = std::max(st, scan_tmp_elems(hist));
+    L.recs_u = S.gathered ? c.take<TileRec>(S.n_u) : L.recs_c;
+    L.recs_t = c.take<TileRec>(S.n_tri[0]);
+    L.ka = c.take<uint32_t>(n);
+    L.va = c.take<uint32_t>(n);
+    L.kb = c.take<uint32_t>(n);
+    L.vb = c.take<uint32_t>(n);
+    L.rank = c.take<uint32_t>(n);
+    L.hist = c.take<uint32_t>(hist);
+    L.hist_scan = c.take<uint64_t>(hist + 1);
+    L.fstart = c.take<uint32_t>(n + 1);
+    L.dag_rng = c.take<uint2>(n);
+    L.dag_col = c.take<uint32_t>(m);
+    L.eid = c.take<uint32_t>(S.NNZ);
+    L.del = c.take<uint32_t>(ceil_div(m, 32) + 1);
+    L.counters = c.take<uint64_t>(2 * (uint64_t)S.count);
+    L.sort_lists = c.take<uint32_t>(3 * n);
+    L.sort_counts = c.take<uint32_t>(4);
+    L.tri_ctr = c.take<uint32_t>(4);
+  }
+  L.scan_tmp = c.take<uint64_t>(st + 1);
+  L.total = c.off;
+  return L;
+}
+
+// The union descriptor (index `count` of the set's table) that makes the
+// orientation write the DAG into the workspace.
+GDesc union_desc(const SetShape& S, const SetLayout& L, void* ws) {
+  GDesc u{};
+  u.vb = 0;
+  u.nv = S.N;
+  u.eb = 0;
+  u.ne = S.NNZ;
+  u.cap = S.NNZ / 2;
+  u.op = 0;
+  u.out_row = at<uint32_t>(ws, L.fstart);
+  u.out_col = at<uint32_t>(ws, L.dag_col);
+  return u;
+}
+
+// ---------------------------------------------------------- profiler
 // Phase timing with HIP events on the call's stream (slim_profile_*).
 struct Profiler {
   std::mutex mu;
@@ -170,7 +200,8 @@ void prof_reset() {
   P.used = 0;
 }
 
-void prof_begin(const char* name, hipStream_t s) {
+void prof_begin(bool on, const char* name, hipStream_t s) {
+  if (!on) return;
   Profiler& P = prof();
   std::lock_guard<std::mutex> lk(P.mu);
   if (!P.on) return;
@@ -180,16 +211,147 @@ void prof_begin(const char* name, hipStream_t s) {
     P.ph.push_back(p);
   }
   P.ph[P.used].name = name;
-  hipEventRecord(P.ph[P.used].a, s);
+  (void)hipEventRecord(P.ph[P.used].a, s);
 }
 
-void prof_end(hipStream_t s) {
+void prof_end(bool on, hipStream_t s) {
+  if (!on) return;
   Profiler& P = prof();
   std::lock_guard<std::mutex> lk(P.mu);
   if (!P.on || P.used >= P.ph.size()) return;
-  hipEventRecord(P.ph[P.used].b, s);
+  (void)hipEventRecord(P.ph[P.used].b, s);
   ++P.used;
 }
+
+// ------------------------------------------------------ the pipeline
+// Enqueues every phase of a set whose header (descriptors and tile
+// prefixes) is already in the workspace.  `row_off`/`col` are the caller's
+// CSR for a single graph; a gathered set builds its union in the workspace.
+void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num_cu, void* ws,
+             const int64_t* row_off, const uint32_t* col, hipStream_t s, bool profile) {
+  const GDesc* gd = at<GDesc>(ws, L.gd);
+  const uint64_t* t0c = at<uint64_t>(ws, L.t0c);
+  uint32_t* tile_cnt = at<uint32_t>(ws, L.tile_cnt);
+  uint64_t* tile_base = at<uint64_t>(ws, L.tile_base);
+  uint64_t* scan_tmp = at<uint64_t>(ws, L.scan_tmp);
+  TileRec* recs_c = at<TileRec>(ws, L.recs_c);
+  const bool tr = S.has_tr && S.NNZ > 0;
+  prof_begin(profile, tr ? "rank" : "sample", s);
+  if (S.gathered) {
+    int64_t* urow = at<int64_t>(ws, L.urow);
+    uint32_t* ucol = at<uint32_t>(ws, L.ucol);
+    gather(gd, S.count, at<uint64_t>(ws, L.vt0), at<uint64_t>(ws, L.et0), S.nvt, S.net, S.N,
+           S.NNZ, urow, ucol, s);
+    row_off = urow;
+    col = ucol;
+  }
+  tile_recs(row_off, gd, t0c, S.count, S.n_c, kTile, recs_c, s);
+  uint32_t* eid = nullptr;
+  uint32_t* del = nullptr;
+  uint64_t* counters = nullptr;
+  if (tr) {
+    uint32_t* rank = at<uint32_t>(ws, L.rank);
+    uint32_t* order = nullptr;
+    degree_rank(row_off, S.N, S.passes, at<uint32_t>(ws, L.ka), at<uint32_t>(ws, L.va),
+                at<uint32_t>(ws, L.kb), at<uint32_t>(ws, L.vb), at<uint32_t>(ws, L.hist),
+                at<uint64_t>(ws, L.hist_scan), scan_tmp, &order, rank, s);
+    prof_end(profile, s);
+    prof_begin(profile, "orient", s);
+    const GDesc* gu = gd + S.count;
+    const uint64_t* t0u = S.gathered ? at<uint64_t>(ws, L.t0u) : t0c;
+    TileRec* recs_u = at<TileRec>(ws, L.recs_u);
+    if (S.gathered) tile_recs(row_off, gu, t0u, 1, S.n_u, kTile, recs_u, s);
+    uint32_t* fstart = at<uint32_t>(ws, L.fstart);
+    uint32_t* dag_col = at<uint32_t>(ws, L.dag_col);
+    uint2* dag_rng = at<uint2>(ws, L.dag_rng);
+    orient(row_off, col, rank, gu, t0u, recs_u, S.n_u, tile_cnt, tile_base, scan_tmp, s);
+    dag_ranges(order, fstart, S.N, dag_rng, s);
+    sort_rows(dag_rng, S.N, dag_col, at<uint32_t>(ws, L.sort_lists),
+              at<uint32_t>(ws, L.sort_counts), num_cu, s);
+    eid = at<uint32_t>(ws, L.eid);
+    del = at<uint32_t>(ws, L.del);
+    counters = at<uint64_t>(ws, L.counters);
+    TileRec* recs_t = at<TileRec>(ws, L.recs_t);
+    const uint64_t n_t = S.n_t(knobs.tri_tile);
+    tile_recs(row_off, gd, at<uint64_t>(ws, L.t0t), S.count, n_t, (uint64_t)knobs.tri_tile,
+              recs_t, s);
+    fill_u32(del, ceil_div(S.NNZ / 2, 32) + 1, 0, s);
+    fill_u32(reinterpret_cast<uint32_t*>(counters), 4 * (uint64_t)S.count, 0, s);
+    prof_end(profile, s);
+    prof_begin(profile, "triangles", s);
+    TriArgs a;
+    a.row_off = row_off;
+    a.col = col;
+    a.rank = rank;
+    a.order = order;
+    a.dag_rng = dag_rng;
+    a.fstart = fstart;
+    a.dag_col = dag_col;
+    a.eid = eid;
+    a.del = del;
+    a.counters = counters;
+    a.gd = gd;
+    a.recs = recs_t;
+    a.ntiles = n_t;
+    triangles(a, at<uint32_t>(ws, L.tri_ctr), num_cu, knobs.tri_blocks_per_cu, knobs.tri_chunk,
+              s);
+    prof_end(profile, s);
+    prof_begin(profile, "compact", s);
+  }
+  compact_out(row_off, col, eid, del, S.NNZ / 2, gd, t0c, recs_c, S.n_c, tile_cnt, tile_base,
+              scan_tmp, s);
+  write_stats(gd, S.count, t0c, counters, tile_base, s);
+  prof_end(profile, s);
+}
+
+// ----------------------------------------------------------- tuning
+bool tune_apply(Tuning& t, const char* key, int64_t value) {
+  const std::string k(key);
+  if (k == "tri_chunk") {
+    if (value < 32 || value > 2048) return false;
+    t.tri_chunk = (int)value;
+  } else if (k == "tri_blocks_per_cu") {
+    if (value < 1 || value > 64) return false;
+    t.tri_blocks_per_cu = (int)value;
+  } else if (k == "tri_tile") {
+    if (value < (int64_t)kTriTileMin || value > (int64_t)tri_tile_max() ||
+        (value & (value - 1)) != 0)
+      return false;
+    t.tri_tile = (int)value;
+  } else {
+    return false;
+  }
+  return true;
+}
+
+bool tune_read(const Tuning& t, const char* key, int64_t* value) {
+  const std::string k(key);
+  if (k == "tri_chunk")
+    *value = t.tri_chunk;
+  else if (k == "tri_blocks_per_cu")
+    *value = t.tri_blocks_per_cu;
+  else if (k == "tri_tile")
+    *value = t.tri_tile;
+  else
+    return false;
+  return true;
+}
+
+Tuning& tuning() {
+  static Tuning t;
+  return t;
+}
+
+std::mutex& tuning_mutex() {
+  static std::mutex m;
+  return m;
+}
+
+}  // namespace slim
+
+using namespace slim;
+
+namespace {
 
 int check_call(const slim_graph* g, double p, void* ws, uint64_t ws_bytes, uint64_t need,
                int64_t* out_ro, uint32_t* out_col) {
@@ -206,11 +368,79 @@ int check_call(const slim_graph* g, double p, void* ws, uint64_t ws_bytes, uint6
   return SLIM_OK;
 }
 
+// The header of a one-graph set, written by one small kernel.
+struct SingleHdr {
+  GDesc gd[2];
+  uint64_t t0c[2];
+  uint64_t t0t[2];
+  uint64_t t0u[2];
+};
+static_assert(sizeof(SingleHdr) <= 256, "one put_bytes launch");
+static_assert(sizeof(GDesc) == 104, "descriptor size");
+
+int single_op(int op, const slim_graph* g, double p, uint64_t seed, void* ws, uint64_t ws_bytes,
+              int64_t* out_ro, uint32_t* out_col, slim_stats_t* stats, hipStream_t s) {
+  const bool tr = op == SLIM_OP_TR;
+  const char* what = tr ? "slim_triangle_reduce" : "slim_edge_sample";
+  const SetShape S = g ? single_shape(g->n, g->nnz, tr) : SetShape{};
+  const uint64_t need = g && g->nnz ? set_layout(S).total : 0;
+  if (int rc = check_call(g, p, ws, ws_bytes, need, out_ro, out_col)) return rc;
+  (void)hipGetLastError();
+  prof_reset();
+  if (g->nnz == 0) {
+    prof_begin(true, tr ? "compact" : "sample", s);
+    fill_i64(out_ro, g->n + 1, 0, s);
+    if (stats) {
+      slim_stats_t st{g->n, 0, 0, 0, 0, 0};
+      put_bytes(stats, &st, sizeof(st), s);
+    }
+    prof_end(true, s);
+    return hip_check(what);
+  }
+  Tuning knobs;
+  {
+    std::lock_guard<std::mutex> lk(tuning_mutex());
+    knobs = tuning();
+  }
+  const SetLayout L = set_layout(S);
+  SingleHdr h{};
+  GDesc& d = h.gd[0];
+  d.vb = 0;
+  d.nv = g->n;
+  d.eb = 0;
+  d.ne = g->nnz;
+  d.thr = threshold(p);
+  d.k0 = (uint32_t)seed;
+  d.k1 = (uint32_t)(seed >> 32);
+  d.op = (uint32_t)op;
+  d.cap = g->nnz;
+  d.in_row = g->row_off;
+  d.in_col = g->col;
+  d.out_row = out_ro;
+  d.out_col = out_col;
+  d.stats = stats;
+  h.gd[1] = union_desc(S, L, ws);
+  h.t0c[0] = 0;
+  h.t0c[1] = S.n_c;
+  h.t0t[0] = 0;
+  h.t0t[1] = S.n_t(knobs.tri_tile);
+  h.t0u[0] = 0;
+  h.t0u[1] = S.n_u;
+  // the packed header of a one-graph set starts with exactly these arrays
+  static_assert(offsetof(SingleHdr, t0c) == 2 * sizeof(GDesc), "layout");
+  if (L.t0c != offsetof(SingleHdr, t0c) || L.t0t != offsetof(SingleHdr, t0t) ||
+      L.t0u != offsetof(SingleHdr, t0u))
+    return fail(SLIM_EDEVICE, "internal: set header layout");
+  put_bytes(at<char>(ws, L.gd), &h, sizeof(h), s);
+  run_set(S, L, knobs, g->num_cu, ws, g->row_off, g->col, s, true);
+  return hip_check(what);
+}
+
 }  // namespace
 
 extern "C" {
 
-const char* slim_last_error(void) { return g_err.c_str(); }
+const char* slim_last_error(void) { return last_error(); }
 
 const char* slim_strerror(int code) {
   switch (code) {
@@ -224,7 +454,7 @@ const char* slim_strerror(int code) {
   }
 }
 
-int slim_version(void) { return 100; }
+int slim_version(void) { return 200; }
 
 int slim_load_csr(const int64_t* d_row_off, const uint32_t* d_col, uint64_t n, uint64_t nnz,
                   uint32_t flags, void* stream, slim_graph_t** out) {
@@ -244,24 +474,37 @@ int slim_load_csr(const int64_t* d_row_off, const uint32_t* d_col, uint64_t n, u
     return fail(SLIM_EDEVICE, "cannot query the CU count");
   if (flags & SLIM_VALIDATE) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const uint64_t ntiles = ceil_div(nnz, slim::kTile);
-    uint32_t* buf = nullptr;
-    if (hipMalloc(&buf, sizeof(uint32_t) * (ntiles + 2)) != hipSuccess)
+    const uint64_t ntiles = tiles_of(nnz, kTile);
+    // err word, then a one-graph set header and its tile records
+    const uint64_t hdr = 256, recs_off = 2 * hdr;
+    const uint64_t bytes = recs_off + sizeof(TileRec) * ntiles;
+    char* buf = nullptr;
+    if (hipMalloc(&buf, bytes) != hipSuccess)
       return fail(SLIM_EDEVICE, "validation buffer allocation failed");
-    uint32_t* err = buf;
-    uint32_t* tile_lo = buf + 1;
+    uint32_t* err = reinterpret_cast<uint32_t*>(buf);
+    GDesc* gd = reinterpret_cast<GDesc*>(buf + hdr);
+    uint64_t* t0 = reinterpret_cast<uint64_t*>(buf + hdr + sizeof(GDesc));
+    TileRec* recs = reinterpret_cast<TileRec*>(buf + recs_off);
     uint32_t h_err = 0;
-    slim::fill_u32(err, 1, 0, s);
-    slim::validate_offsets(d_row_off, n, nnz, err, s);
+    fill_u32(err, 1, 0, s);
+    validate_offsets(d_row_off, n, nnz, err, s);
     hipError_t e = hipMemcpyAsync(&h_err, err, sizeof(h_err), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess && h_err == 0 && nnz) {
-      slim::tile_lo_build(d_row_off, n, nnz, ntiles, tile_lo, s);
-      slim::validate_entries(d_row_off, d_col, n, nnz, ntiles, tile_lo, err, s);
+      struct {
+        GDesc d;
+        uint64_t t0[2];
+      } h{};
+      h.d.nv = n;
+      h.d.ne = nnz;
+      h.t0[1] = ntiles;
+      put_bytes(gd, &h, sizeof(h), s);
+      tile_recs(d_row_off, gd, t0, 1, ntiles, kTile, recs, s);
+      validate_entries(d_row_off, d_col, n, recs, ntiles, err, s);
       e = hipMemcpyAsync(&h_err, err, sizeof(h_err), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
-    hipFree(buf);
+    (void)hipFree(buf);
     if (e != hipSuccess) return fail(SLIM_EDEVICE, "validation: %s", hipGetErrorString(e));
     if (h_err) {
       const char* what = (h_err & 1)    ? "row offsets are not monotone from 0 to nnz"
@@ -282,113 +525,23 @@ void slim_graph_free(slim_graph_t* g) { delete g; }
 
 int slim_workspace_size(const slim_graph_t* g, int op, uint64_t* bytes) {
   if (!g || !bytes) return fail(SLIM_EINVAL, "NULL argument");
-  if (op == SLIM_OP_TR)
-    *bytes = g->nnz ? tr_layout(g->n, g->nnz).total : 0;
-  else if (op == SLIM_OP_ES)
-    *bytes = g->nnz ? es_layout(g->nnz).total : 0;
-  else
-    return fail(SLIM_EINVAL, "unknown op %d", op);
+  if (op != SLIM_OP_TR && op != SLIM_OP_ES) return fail(SLIM_EINVAL, "unknown op %d", op);
+  *bytes = g->nnz ? set_layout(single_shape(g->n, g->nnz, op == SLIM_OP_TR)).total : 0;
   return ok();
 }
 
 int slim_triangle_reduce(const slim_graph_t* g, double p, uint64_t seed, void* d_ws,
                          uint64_t ws_bytes, int64_t* d_out_row_off, uint32_t* d_out_col,
                          slim_stats_t* d_stats, void* stream) {
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const uint64_t need = g && g->nnz ? tr_layout(g->n, g->nnz).total : 0;
-  if (int rc = check_call(g, p, d_ws, ws_bytes, need, d_out_row_off, d_out_col)) return rc;
-  (void)hipGetLastError();
-  const uint64_t n = g->n, nnz = g->nnz;
-  if (nnz == 0) {
-    slim::fill_i64(d_out_row_off, n + 1, 0, s);
-    slim::write_stats(n, 0, nullptr, nullptr, d_stats, s);
-    return hip_check("slim_triangle_reduce");
-  }
-  const TrLayout L = tr_layout(n, nnz);
-  prof_reset();
-  prof_begin("rank", s);
-  uint32_t* rank = at<uint32_t>(d_ws, L.rank);
-  uint32_t* order = nullptr;
-  uint64_t* scan_tmp = at<uint64_t>(d_ws, L.scan_tmp);
-  slim::degree_rank(g->row_off, n, L.passes, at<uint32_t>(d_ws, L.ka), at<uint32_t>(d_ws, L.va),
-                    at<uint32_t>(d_ws, L.kb), at<uint32_t>(d_ws, L.vb),
-                    at<uint32_t>(d_ws, L.hist), at<uint64_t>(d_ws, L.hist_scan), scan_tmp,
-                    &order, rank, s);
-  prof_end(s);
-  prof_begin("orient", s);
-  uint32_t* tile_lo = at<uint32_t>(d_ws, L.tile_lo);
-  uint32_t* tile_cnt = at<uint32_t>(d_ws, L.tile_cnt);
-  uint64_t* tile_base = at<uint64_t>(d_ws, L.tile_base);
-  uint32_t* fstart = at<uint32_t>(d_ws, L.fstart);
-  uint32_t* dag_col = at<uint32_t>(d_ws, L.dag_col);
-  uint32_t* eid = at<uint32_t>(d_ws, L.eid);
-  uint32_t* del = at<uint32_t>(d_ws, L.del);
-  uint64_t* counters = at<uint64_t>(d_ws, L.counters);
-  uint2* dag_rng = at<uint2>(d_ws, L.dag_rng);
-  slim::tile_lo_build(g->row_off, n, nnz, L.ntiles, tile_lo, s);
-  slim::orient(g->row_off, g->col, rank, n, nnz, L.ntiles, tile_lo, tile_cnt, tile_base, scan_tmp,
-               dag_col, eid, fstart, s);
-  slim::dag_ranges(order, fstart, n, dag_rng, s);
-  slim::sort_rows(dag_rng, n, dag_col, at<uint32_t>(d_ws, L.sort_lists),
-                  at<uint32_t>(d_ws, L.sort_counts), g->num_cu, s);
-  uint32_t* tri_tlo = at<uint32_t>(d_ws, L.tri_tlo);
-  slim::tile_lo_build(g->row_off, n, nnz, slim::tri_tiles(nnz), tri_tlo, s,
-                      slim::tri_tile_entries());
-  slim::fill_u32(del, ceil_div(nnz / 2, 32) + 1, 0, s);
-  slim::fill_u32(reinterpret_cast<uint32_t*>(counters), 8, 0, s);
-  prof_end(s);
-  slim::TriArgs a;
-  a.row_off = g->row_off;
-  a.col = g->col;
-  a.rank = rank;
-  a.order = order;
-  a.dag_rng = dag_rng;
-  a.fstart = fstart;
-  a.dag_col = dag_col;
-  a.eid = eid;
-  a.del = del;
-  a.counters = counters;
-  a.n = n;
-  a.nnz = nnz;
-  a.thr = threshold(p);
-  a.k0 = (uint32_t)seed;
-  a.k1 = (uint32_t)(seed >> 32);
-  prof_begin("triangles", s);
-  slim::triangles(a, tri_tlo, at<uint32_t>(d_ws, L.tri_ctr), g->num_cu, s);
-  prof_end(s);
-  prof_begin("compact", s);
-  slim::compact_tr(g->row_off, g->col, eid, del, n, nnz, L.ntiles, tile_lo, tile_cnt, tile_base,
-                   scan_tmp, d_out_col, d_out_row_off, s);
-  slim::write_stats(n, nnz, counters, tile_base + L.ntiles, d_stats, s);
-  prof_end(s);
-  return hip_check("slim_triangle_reduce");
+  return single_op(SLIM_OP_TR, g, p, seed, d_ws, ws_bytes, d_out_row_off, d_out_col, d_stats,
+                   static_cast<hipStream_t>(stream));
 }
 
 int slim_edge_sample(const slim_graph_t* g, double p, uint64_t seed, void* d_ws,
                      uint64_t ws_bytes, int64_t* d_out_row_off, uint32_t* d_out_col,
                      slim_stats_t* d_stats, void* stream) {
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const uint64_t need = g && g->nnz ? es_layout(g->nnz).total : 0;
-  if (int rc = check_call(g, p, d_ws, ws_bytes, need, d_out_row_off, d_out_col)) return rc;
-  (void)hipGetLastError();
-  const uint64_t n = g->n, nnz = g->nnz;
-  if (nnz == 0) {
-    slim::fill_i64(d_out_row_off, n + 1, 0, s);
-    slim::write_stats(n, 0, nullptr, nullptr, d_stats, s);
-    return hip_check("slim_edge_sample");
-  }
-  const EsLayout L = es_layout(nnz);
-  prof_reset();
-  prof_begin("sample", s);
-  uint32_t* tile_lo = at<uint32_t>(d_ws, L.tile_lo);
-  uint64_t* tile_base = at<uint64_t>(d_ws, L.tile_base);
-  slim::tile_lo_build(g->row_off, n, nnz, L.ntiles, tile_lo, s);
-  slim::compact_es(g->row_off, g->col, threshold(p), seed, n, nnz, L.ntiles, tile_lo,
-                   at<uint32_t>(d_ws, L.tile_cnt), tile_base, at<uint64_t>(d_ws, L.scan_tmp),
-                   d_out_col, d_out_row_off, s);
-  slim::write_stats(n, nnz, nullptr, tile_base + L.ntiles, d_stats, s);
-  prof_end(s);
-  return hip_check("slim_edge_sample");
+  return single_op(SLIM_OP_ES, g, p, seed, d_ws, ws_bytes, d_out_row_off, d_out_col, d_stats,
+                   static_cast<hipStream_t>(stream));
 }
 
 int slim_profile_enable(int on) {
@@ -418,38 +571,18 @@ int slim_profile_read(slim_phase_t* out, int max, int* count) {
 
 int slim_tune_set(const char* key, int64_t value) {
   if (!key) return fail(SLIM_EINVAL, "key is NULL");
-  slim::Tuning& t = slim::tuning();
-  std::string k(key);
-  if (k == "tri_chunk") {
-    if (value < 32 || value > 2048) return fail(SLIM_EINVAL, "tri_chunk must lie in [32, 2048]");
-    t.tri_chunk = (int)value;
-  } else if (k == "tri_blocks_per_cu") {
-    if (value < 1 || value > 64) return fail(SLIM_EINVAL, "tri_blocks_per_cu must lie in [1, 64]");
-    t.tri_blocks_per_cu = (int)value;
-  } else {
-    return fail(SLIM_EINVAL, "unknown knob '%s'", key);
-  }
+  std::lock_guard<std::mutex> lk(tuning_mutex());
+  if (!tune_apply(tuning(), key, value))
+    return fail(SLIM_EINVAL, "unknown knob '%s' or value %lld out of range", key,
+                (long long)value);
   return ok();
 }
 
 int slim_tune_get(const char* key, int64_t* value) {
   if (!key || !value) return fail(SLIM_EINVAL, "NULL argument");
-  const slim::Tuning& t = slim::tuning();
-  std::string k(key);
-  if (k == "tri_chunk")
-    *value = t.tri_chunk;
-  else if (k == "tri_blocks_per_cu")
-    *value = t.tri_blocks_per_cu;
-  else
-    return fail(SLIM_EINVAL, "unknown knob '%s'", key);
+  std::lock_guard<std::mutex> lk(tuning_mutex());
+  if (!tune_read(tuning(), key, value)) return fail(SLIM_EINVAL, "unknown knob '%s'", key);
   return ok();
 }
 
 }  // extern "C"
-
-namespace slim {
-Tuning& tuning() {
-  static Tuning t;
-  return t;
-}
-}  // namespace slim

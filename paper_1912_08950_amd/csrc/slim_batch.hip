@@ -1,0 +1,410 @@
+// Batches (slim_batch_*): many graphs as one graph set.  The host builds
+// the set header (per-graph descriptors and tile prefixes), a run refreshes
+// it in the workspace with one copy when it changed, and the launch sequence
+// of the set is captured once into a HIP graph and replayed.
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "slim_batch.h"
+
+using namespace slim;
+
+struct slim_batch {
+  int device = 0;
+  int num_cu = 0;
+  uint32_t count = 0;
+  std::vector<GDesc> gd;  // count + 1; the last is the union (filled per run)
+  std::vector<uint64_t> t0c, vt0, et0;
+  std::vector<uint64_t> ne;  // per graph, for the triangle tile prefixes
+  SetShape shape;
+  SetLayout layout{};
+  Tuning knobs;
+  bool use_graph = true;
+  // header upload
+  std::vector<char> hdr, last_hdr;
+  void* pinned = nullptr;
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+  void* last_ws = nullptr;
+  // captured launch sequence
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* cap_ws = nullptr;
+  Tuning cap_knobs;
+};
+
+namespace {
+
+bool same_knobs(const Tuning& a, const Tuning& b) {
+  return a.tri_chunk == b.tri_chunk && a.tri_blocks_per_cu == b.tri_blocks_per_cu &&
+         a.tri_tile == b.tri_tile;
+}
+
+void drop_graph(slim_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->cap_ws = nullptr;
+}
+
+// Fills the host copy of the set header for workspace `ws` and outputs.
+void build_header(slim_batch* b, void* ws, const slim_out_t* outs) {
+  const SetLayout& L = b->layout;
+  const uint32_t cnt = b->count;
+  b->hdr.assign(L.hdr_bytes, 0);
+  char* h = b->hdr.data();
+  GDesc* gd = reinterpret_cast<GDesc*>(h + L.gd);
+  for (uint32_t g = 0; g < cnt; ++g) {
+    gd[g] = b->gd[g];
+    gd[g].out_row = outs[g].row_off;
+    gd[g].out_col = outs[g].col;
+    gd[g].stats = outs[g].stats;
+  }
+  gd[cnt] = union_desc(b->shape, L, ws);
+  uint64_t* t0c = reinterpret_cast<uint64_t*>(h + L.t0c);
+  uint64_t* t0t = reinterpret_cast<uint64_t*>(h + L.t0t);
+  uint64_t* t0u = reinterpret_cast<uint64_t*>(h + L.t0u);
+  uint64_t* vt0 = reinterpret_cast<uint64_t*>(h + L.vt0);
+  uint64_t* et0 = reinterpret_cast<uint64_t*>(h + L.et0);
+  uint64_t acc = 0;
+  for (uint32_t g = 0; g <= cnt; ++g) {
+    t0c[g] = b->t0c[g];
+    vt0[g] = b->vt0[g];
+    et0[g] = b->et0[g];
+    t0t[g] = acc;
+    if (g < cnt) acc += tiles_of(b->ne[g], (uint64_t)b->knobs.tri_tile);
+  }
+  t0u[0] = 0;
+  t0u[1] = b->shape.n_u;
+}
+
+int check_run(const slim_batch* b, void* ws, uint64_t ws_bytes, const slim_out_t* outs) {
+  if (!b) return fail(SLIM_EINVAL, "batch is NULL");
+  if (!outs) return fail(SLIM_EINVAL, "outs is NULL");
+  if (ws_bytes < b->layout.total)
+    return fail(SLIM_ENOMEM, "workspace has %llu bytes, %llu needed",
+                (unsigned long long)ws_bytes, (unsigned long long)b->layout.total);
+  if (!ws) return fail(SLIM_EINVAL, "d_ws is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(SLIM_EINVAL, "d_ws must be 256-byte aligned");
+  for (uint32_t g = 0; g < b->count; ++g) {
+    if (!outs[g].row_off) return fail(SLIM_EINVAL, "outs[%u].row_off is NULL", g);
+    if (b->gd[g].ne && !outs[g].col) return fail(SLIM_EINVAL, "outs[%u].col is NULL", g);
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
+    return fail(SLIM_EINVAL, "the batch lives on device %d, current device is %d", b->device, dev);
+  return SLIM_OK;
+}
+
+int run(slim_batch* b, void* ws, uint64_t ws_bytes, const slim_out_t* outs, hipStream_t s) {
+  if (int rc = check_run(b, ws, ws_bytes, outs)) return rc;
+  (void)hipGetLastError();
+  build_header(b, ws, outs);
+  const size_t hb = b->hdr.size();
+  if (ws != b->last_ws || b->hdr != b->last_hdr) {
+    // the pinned buffer may still feed the previous upload
+    if (b->upload_pending && hipEventSynchronize(b->upload_done) != hipSuccess)
+      return fail(SLIM_EDEVICE, "batch header: previous upload failed");
+    std::memcpy(b->pinned, b->hdr.data(), hb);
+    if (hipMemcpyAsync(ws, b->pinned, hb, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipEventRecord(b->upload_done, s) != hipSuccess)
+      return fail(SLIM_EDEVICE, "batch header upload failed");
+    b->upload_pending = true;
+    b->last_hdr = b->hdr;
+    b->last_ws = ws;
+  }
+  if (!b->use_graph) {
+    run_set(b->shape, b->layout, b->knobs, b->num_cu, ws, nullptr, nullptr, s, false);
+    return hip_check("slim_batch_run");
+  }
+  if (!b->exec || b->cap_ws != ws || !same_knobs(b->cap_knobs, b->knobs)) {
+    drop_graph(b);
+    if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+      return fail(SLIM_EDEVICE, "hipStreamBeginCapture failed");
+    run_set(b->shape, b->layout, b->knobs, b->num_cu, ws, nullptr, nullptr, b->cap_stream, false);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &gr);
+    if (e != hipSuccess || !gr) {
+      (void)hipGetLastError();
+      return fail(SLIM_EDEVICE, "capture of the batch failed: %s", hipGetErrorString(e));
+    }
+    b->graph = gr;
+    e = hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      b->exec = nullptr;
+      drop_graph(b);
+      return fail(SLIM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    b->cap_ws = ws;
+    b->cap_knobs = b->knobs;
+  }
+  if (hipGraphLaunch(b->exec, s) != hipSuccess) return fail(SLIM_EDEVICE, "hipGraphLaunch failed");
+  return hip_check("slim_batch_run");
+}
+
+std::string tune_key(const slim_batch* b) {
+  hipDeviceProp_t prop{};
+  (void)hipGetDeviceProperties(&prop, b->device);
+  std::ostringstream k;
+  k << prop.gcnArchName << ":" << b->num_cu << ":" << b->count << ":" << b->shape.N << ":"
+    << b->shape.NNZ << ":" << (b->shape.has_tr ? "tr" : "es");
+  std::string s = k.str();
+  for (char& c : s)
+    if (c == ' ' || c == '\t' || c == '\n') c = '_';
+  return s;
+}
+
+bool tune_lookup(const char* path, const std::string& key, Tuning& t) {
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {  // the last matching line wins
+    std::istringstream is(line);
+    std::string k;
+    if (!(is >> k) || k != key) continue;
+    Tuning c = t;
+    std::string kv;
+    bool good = true;
+    while (is >> kv) {
+      const size_t eq = kv.find('=');
+      if (eq == std::string::npos) {
+        good = false;
+        break;
+      }
+      const std::string name = kv.substr(0, eq);
+      const long long v = std::atoll(kv.c_str() + eq + 1);
+      if (!tune_apply(c, name.c_str(), v)) good = false;
+    }
+    if (good) {
+      t = c;
+      found = true;
+    }
+  }
+  return found;
+}
+
+}  // namespace
+
+extern "C" {
+
+int slim_batch_create(const slim_graph_t* const* graphs, const slim_job_params_t* jobs,
+                      uint32_t count, slim_batch_t** out) {
+  if (!out) return fail(SLIM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!graphs || !jobs) return fail(SLIM_EINVAL, "graphs or jobs is NULL");
+  if (count == 0) return fail(SLIM_EINVAL, "a batch needs at least one graph");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(SLIM_EDEVICE, "hipGetDevice failed");
+  slim_batch* b = new (std::nothrow) slim_batch;
+  if (!b) return fail(SLIM_ENOMEM, "out of host memory");
+  b->device = dev;
+  b->count = count;
+  b->gd.resize(count + 1);
+  b->t0c.resize(count + 1);
+  b->vt0.resize(count + 1);
+  b->et0.resize(count + 1);
+  b->ne.resize(count);
+  SetShape& S = b->shape;
+  S.count = count;
+  S.gathered = true;
+  uint64_t N = 0, NNZ = 0, maxdeg = 0;
+  for (uint32_t g = 0; g < count; ++g) {
+    const slim_graph* G = graphs[g];
+    const slim_job_params_t& J = jobs[g];
+    if (!G) {
+      delete b;
+      return fail(SLIM_EINVAL, "graphs[%u] is NULL", g);
+    }
+    if (G->device != dev) {
+      delete b;
+      return fail(SLIM_EINVAL, "graphs[%u] lives on device %d, not %d", g, G->device, dev);
+    }
+    if ((J.op != SLIM_OP_TR && J.op != SLIM_OP_ES) || J.pad != 0) {
+      delete b;
+      return fail(SLIM_EINVAL, "jobs[%u]: bad op %d", g, J.op);
+    }
+    if (check_p(J.p)) {
+      delete b;
+      return SLIM_EINVAL;
+    }
+    b->num_cu = G->num_cu;
+    GDesc& d = b->gd[g];
+    d = GDesc{};
+    d.vb = N;
+    d.nv = G->n;
+    d.eb = NNZ;
+    d.ne = G->nnz;
+    d.thr = threshold(J.p);
+    d.k0 = (uint32_t)J.seed;
+    d.k1 = (uint32_t)(J.seed >> 32);
+    d.op = (uint32_t)J.op;
+    d.cap = G->nnz;
+    d.in_row = G->row_off;
+    d.in_col = G->col;
+    b->ne[g] = G->nnz;
+    b->t0c[g] = S.n_c;
+    b->vt0[g] = S.nvt;
+    b->et0[g] = S.net;
+    S.n_c += tiles_of(G->nnz, kTile);
+    for (int i = 0; i < 3; ++i) S.n_tri[i] += tiles_of(G->nnz, kTriTileMin << i);
+    S.nvt += (G->n + kTile - 1) / kTile;
+    S.net += (G->nnz + kTile - 1) / kTile;
+    if (J.op == SLIM_OP_TR) S.has_tr = true;
+    uint64_t md = G->n > 0 ? G->n - 1 : 0;
+    if (G->nnz < md) md = G->nnz;
+    if (md > maxdeg) maxdeg = md;
+    N += G->n;
+    NNZ += G->nnz;
+  }
+  b->t0c[count] = S.n_c;
+  b->vt0[count] = S.nvt;
+  b->et0[count] = S.net;
+  if (N > 0xffffffffull || NNZ / 2 > 0xffffffffull) {
+    delete b;
+    return fail(SLIM_EINVAL, "batch union too large: n = %llu, m = %llu (limit 2^32-1 each)",
+                (unsigned long long)N, (unsigned long long)(NNZ / 2));
+  }
+  S.N = N;
+  S.NNZ = NNZ;
+  S.n_u = tiles_of(NNZ, kTile);
+  S.passes = radix_passes(maxdeg);
+  b->layout = set_layout(S);
+  {
+    std::lock_guard<std::mutex> lk(tuning_mutex());
+    b->knobs = tuning();
+  }
+  if (hipHostMalloc(&b->pinned, b->layout.hdr_bytes, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    slim_batch_free(b);
+    return fail(SLIM_EDEVICE, "batch: host buffer, event or stream creation failed");
+  }
+  *out = b;
+  return ok();
+}
+
+int slim_batch_workspace_size(const slim_batch_t* b, uint64_t* bytes) {
+  if (!b || !bytes) return fail(SLIM_EINVAL, "NULL argument");
+  *bytes = b->layout.total;
+  return ok();
+}
+
+int slim_batch_run(slim_batch_t* b, void* d_ws, uint64_t ws_bytes, const slim_out_t* outs,
+                   void* stream) {
+  return run(b, d_ws, ws_bytes, outs, static_cast<hipStream_t>(stream));
+}
+
+int slim_batch_set(slim_batch_t* b, const char* key, int64_t value) {
+  if (!b || !key) return fail(SLIM_EINVAL, "NULL argument");
+  if (std::strcmp(key, "use_graph") == 0) {
+    if (value != 0 && value != 1) return fail(SLIM_EINVAL, "use_graph must be 0 or 1");
+    b->use_graph = value != 0;
+    return ok();
+  }
+  if (!tune_apply(b->knobs, key, value))
+    return fail(SLIM_EINVAL, "unknown knob '%s' or value %lld out of range", key,
+                (long long)value);
+  return ok();
+}
+
+int slim_batch_get(const slim_batch_t* b, const char* key, int64_t* value) {
+  if (!b || !key || !value) return fail(SLIM_EINVAL, "NULL argument");
+  if (std::strcmp(key, "use_graph") == 0) {
+    *value = b->use_graph ? 1 : 0;
+    return ok();
+  }
+  if (!tune_read(b->knobs, key, value)) return fail(SLIM_EINVAL, "unknown knob '%s'", key);
+  return ok();
+}
+
+int slim_batch_tune(slim_batch_t* b, void* d_ws, uint64_t ws_bytes, const slim_out_t* outs,
+                    const char* cache_path, void* stream) {
+  if (int rc = check_run(b, d_ws, ws_bytes, outs)) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const std::string key = tune_key(b);
+  if (cache_path && tune_lookup(cache_path, key, b->knobs)) {
+    if (int rc = run(b, d_ws, ws_bytes, outs, s)) return rc;
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(SLIM_EDEVICE, "tune: sync failed");
+    return ok();
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(SLIM_EDEVICE, "tune: event creation failed");
+  // best of two timed replays after one untimed run (which captures)
+  auto time_cfg = [&](const Tuning& t, float* ms) -> int {
+    b->knobs = t;
+    if (int rc = run(b, d_ws, ws_bytes, outs, s)) return rc;
+    float best = 1e30f;
+    for (int r = 0; r < 2; ++r) {
+      if (hipEventRecord(e0, s) != hipSuccess) return fail(SLIM_EDEVICE, "tune: event");
+      if (int rc = run(b, d_ws, ws_bytes, outs, s)) return rc;
+      float x = 0.f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&x, e0, e1) != hipSuccess)
+        return fail(SLIM_EDEVICE, "tune: timing failed");
+      if (x < best) best = x;
+    }
+    *ms = best;
+    return SLIM_OK;
+  };
+  Tuning best = b->knobs;
+  float best_ms = 0.f;
+  int rc = SLIM_OK;
+  if (b->shape.has_tr && b->shape.NNZ > 0) {
+    rc = time_cfg(best, &best_ms);
+    const int tiles[] = {1024, 512, 256};
+    const int bpcs[] = {1, 2, 3, 4};
+    const int chunks[] = {2048, 1024, 512};
+    for (int dim = 0; dim < 3 && rc == SLIM_OK; ++dim) {
+      const int* vals = dim == 0 ? tiles : dim == 1 ? bpcs : chunks;
+      const int nv = dim == 1 ? 4 : 3;
+      for (int i = 0; i < nv && rc == SLIM_OK; ++i) {
+        Tuning c = best;
+        if (dim == 0) c.tri_tile = vals[i];
+        if (dim == 1) c.tri_blocks_per_cu = vals[i];
+        if (dim == 2) c.tri_chunk = vals[i];
+        if (same_knobs(c, best)) continue;
+        float ms = 0.f;
+        rc = time_cfg(c, &ms);
+        if (rc == SLIM_OK && ms < best_ms) {
+          best = c;
+          best_ms = ms;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != SLIM_OK) return rc;
+  b->knobs = best;
+  if ((rc = run(b, d_ws, ws_bytes, outs, s)) != SLIM_OK) return rc;
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(SLIM_EDEVICE, "tune: sync failed");
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    if (!f) return fail(SLIM_EINVAL, "cannot append to tuning cache '%s'", cache_path);
+    f << key << " tri_tile=" << best.tri_tile << " tri_blocks_per_cu=" << best.tri_blocks_per_cu
+      << " tri_chunk=" << best.tri_chunk << "\n";
+  }
+  return ok();
+}
+
+void slim_batch_free(slim_batch_t* b) {
+  if (!b) return;
+  drop_graph(b);
+  if (b->upload_done) {
+    (void)hipEventSynchronize(b->upload_done);
+    (void)hipEventDestroy(b->upload_done);
+  }
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->pinned) (void)hipHostFree(b->pinned);
+  delete b;
+}
+
+}  // extern "C"

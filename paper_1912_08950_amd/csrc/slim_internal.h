@@ -1,4 +1,13 @@
-// Host-side launchers shared between the libslim translation units.
+// Host-side launchers and device records shared between the libslim
+// translation units.
+//
+// Every compute call works on a *graph set*: one or more graphs laid out
+// back to back in a union CSR (graph g owns vertices [vb, vb+nv) and CSR
+// entries [eb, eb+ne) of the union, with union vertex ids in the columns).
+// A single-graph call is a set of one whose union is the caller's CSR; a
+// batch gathers its graphs into a union first.  Work tiles never straddle
+// two graphs, so the graph of a tile -- its random key, threshold, output
+// arrays and counters -- is a per-tile constant.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,6 +17,34 @@
 #include "slim_device.h"
 
 namespace slim {
+
+// One graph of a set.
+struct GDesc {
+  uint64_t vb, nv;         // union vertices [vb, vb + nv)
+  uint64_t eb, ne;         // union CSR entries [eb, eb + ne)
+  uint64_t thr;            // triangle selected / edge deleted iff Philox word 0 < thr
+  uint32_t k0, k1;         // Philox key (seed)
+  uint32_t op;             // SLIM_OP_TR or SLIM_OP_ES
+  uint32_t pad;
+  uint64_t cap;            // capacity of out_col in entries
+  const int64_t* in_row;   // the graph's own CSR (gather source of a batch)
+  const uint32_t* in_col;
+  void* out_row;           // row starts, nv + 1 (int64; uint32 for the DAG)
+  uint32_t* out_col;       // columns, local ids
+  slim_stats_t* stats;     // optional
+};
+
+// One work tile: union entries [j0, j0 + span) of graph g.  It owns the row
+// starts of union rows [lo, hi); the last tile of a graph owns the rows up
+// to the graph's end and also writes the graph's end offset.
+struct TileRec {
+  int64_t j0;
+  uint32_t span;
+  uint32_t g;
+  uint32_t lo, hi;
+  uint32_t last;
+  uint32_t pad;
+};
 
 void fill_u32(uint32_t* p, uint64_t len, uint32_t v, hipStream_t s);
 void fill_i64(int64_t* p, uint64_t len, int64_t v, hipStream_t s);
@@ -21,28 +58,40 @@ void degree_rank(const int64_t* row_off, uint64_t n, int passes, uint32_t* ka, u
                  uint32_t* kb, uint32_t* vb, uint32_t* hist, uint64_t* hist_scan,
                  uint64_t* scan_tmp, uint32_t** order_out, uint32_t* rank, hipStream_t s);
 
-void tile_lo_build(const int64_t* row_off, uint64_t n, uint64_t nnz, uint64_t ntiles,
-                   uint32_t* tile_lo, hipStream_t s, uint64_t tile = kTile);
-void orient(const int64_t* row_off, const uint32_t* col, const uint32_t* rank, uint64_t n,
-            uint64_t nnz, uint64_t ntiles, const uint32_t* tile_lo, uint32_t* tile_cnt,
-            uint64_t* tile_base, uint64_t* scan_tmp, uint32_t* dag_col, uint32_t* eid,
-            uint32_t* fstart, hipStream_t s);
+// Copies up to 256 bytes of host data (descriptors) to device memory by a
+// kernel launch: no host-to-device copy, so it can sit in a captured graph.
+void put_bytes(void* dst, const void* src, uint32_t bytes, hipStream_t s);
+// Tile records of a set with `tile` entries per tile; tile0[g] is the first
+// tile of graph g (tile0[count] = ntiles; every graph has at least one tile).
+void tile_recs(const int64_t* row_off, const GDesc* gd, const uint64_t* tile0, uint32_t count,
+               uint64_t ntiles, uint64_t tile, TileRec* recs, hipStream_t s);
+// Gathers the graphs of a set into the union CSR (union ids in ucol).
+// vtile0 / etile0: per-graph prefixes of kTile-sized vertex / entry chunks.
+void gather(const GDesc* gd, uint32_t count, const uint64_t* vtile0, const uint64_t* etile0,
+            uint64_t nvt, uint64_t net, uint64_t N, uint64_t NNZ, int64_t* urow, uint32_t* ucol,
+            hipStream_t s);
+
+// DAG: dag_col = rank ids of the forward entries, fstart = row starts.
+void orient(const int64_t* row_off, const uint32_t* col, const uint32_t* rank,
+            const GDesc* gd_union, const uint64_t* tile0, const TileRec* recs, uint64_t ntiles,
+            uint32_t* tile_cnt, uint64_t* tile_base, uint64_t* scan_tmp, hipStream_t s);
 void dag_ranges(const uint32_t* order, const uint32_t* fstart, uint64_t n, uint2* dag_rng,
                 hipStream_t s);
-void compact_tr(const int64_t* row_off, const uint32_t* col, const uint32_t* eid,
-                const uint32_t* del, uint64_t n, uint64_t nnz, uint64_t ntiles,
-                const uint32_t* tile_lo, uint32_t* tile_cnt, uint64_t* tile_base,
-                uint64_t* scan_tmp, uint32_t* out_col, int64_t* out_row_off, hipStream_t s);
-void compact_es(const int64_t* row_off, const uint32_t* col, uint64_t thr, uint64_t seed,
-                uint64_t n, uint64_t nnz, uint64_t ntiles, const uint32_t* tile_lo,
-                uint32_t* tile_cnt, uint64_t* tile_base, uint64_t* scan_tmp, uint32_t* out_col,
-                int64_t* out_row_off, hipStream_t s);
-void write_stats(uint64_t n, uint64_t nnz, const uint64_t* counters, const uint64_t* kept,
-                 slim_stats_t* st, hipStream_t s);
+// Output CSRs of every graph of the set: TR graphs keep the entries whose
+// edge is unmarked, ES graphs the entries whose edge is not sampled out.
+// eid/del may be NULL when the set has no TR graph.
+void compact_out(const int64_t* row_off, const uint32_t* col, const uint32_t* eid,
+                 const uint32_t* del, uint64_t m, const GDesc* gd, const uint64_t* tile0,
+                 const TileRec* recs, uint64_t ntiles, uint32_t* tile_cnt, uint64_t* tile_base,
+                 uint64_t* scan_tmp, hipStream_t s);
+// Per-graph stats from the triangle counters (2 per graph, may be NULL) and
+// the compaction's tile scan.
+void write_stats(const GDesc* gd, uint32_t count, const uint64_t* tile0,
+                 const uint64_t* counters, const uint64_t* tile_base, hipStream_t s);
 void validate_offsets(const int64_t* row_off, uint64_t n, uint64_t nnz, uint32_t* err,
                       hipStream_t s);
-void validate_entries(const int64_t* row_off, const uint32_t* col, uint64_t n, uint64_t nnz,
-                      uint64_t ntiles, const uint32_t* tile_lo, uint32_t* err, hipStream_t s);
+void validate_entries(const int64_t* row_off, const uint32_t* col, uint64_t n,
+                      const TileRec* recs, uint64_t ntiles, uint32_t* err, hipStream_t s);
 
 // Every DAG row is sorted by rank id (slim_sort.hip); rows of length up to
 // kSortMin by one thread each.
@@ -57,26 +106,28 @@ struct TriArgs {
   const uint32_t* rank;
   const uint32_t* order;
   const uint2* dag_rng;    // DAG row of each rank id
-  const uint32_t* fstart;  // DAG row start of each original id (n+1)
+  const uint32_t* fstart;  // DAG row start of each union id (N+1)
   const uint32_t* dag_col;
-  uint32_t* eid;       // backward CSR entries get their DAG position here
-  uint32_t* del;       // deletion bitmap over DAG positions
-  uint64_t* counters;  // [0] triangles, [1] selected
-  uint64_t n;
-  uint64_t nnz;
-  uint64_t thr;
-  uint32_t k0, k1;
+  uint32_t* eid;           // backward CSR entries get their DAG position here
+  uint32_t* del;           // deletion bitmap over DAG positions
+  uint64_t* counters;      // per graph: [2g] triangles, [2g+1] selected
+  const GDesc* gd;
+  const TileRec* recs;     // graph-aligned tiles of at most tri_tile_max() entries
+  uint64_t ntiles;
 };
-uint64_t tri_tiles(uint64_t nnz);
-uint64_t tri_tile_entries();
-void triangles(const TriArgs& a, const uint32_t* tlo, uint32_t* tile_ctr, int num_cu,
-               hipStream_t s);
+uint64_t tri_tile_max();
+void triangles(const TriArgs& a, uint32_t* tile_ctr, int num_cu, int blocks_per_cu,
+               int chunk, hipStream_t s);
 
-// Scheduling knobs (slim_tune_set); never change results.
+// Scheduling knobs; never change results.
 struct Tuning {
-  int tri_chunk = 2048;
-  int tri_blocks_per_cu = 2;
+  int tri_chunk = 2048;       // out-list entries hashed per pass
+  int tri_blocks_per_cu = 2;  // resident blocks of the triangle kernel per CU
+  int tri_tile = 1024;        // CSR entries per triangle tile (a power of two, 256..1024)
 };
 Tuning& tuning();
+// Checks a knob value; returns false if `key` is unknown or out of range.
+bool tune_apply(Tuning& t, const char* key, int64_t value);
+bool tune_read(const Tuning& t, const char* key, int64_t* value);
 
 }  // namespace slim

@@ -1,12 +1,13 @@
-// HIP kernels of libslim (gfx950): degree-rank relabelling, DAG orientation,
-// triangle listing with selection and deletion marks, and CSR compaction.
+// HIP kernels of libslim (gfx950): graph-set tiles and gather, degree-rank
+// relabelling, DAG orientation, CSR compaction and per-graph stats.
 //
-// Data layout (all in HBM, caller-provided workspace):
-//   rank[n], order[n]   old id -> rank id and back; rank order = (degree, id)
+// Data layout (all in HBM, caller-provided workspace), over the union CSR of
+// the set (n vertices, nnz entries, m = nnz/2 edges):
+//   rank[n], order[n]   union id -> rank id and back; rank order = (degree, id)
 //   dag_col[m]          rank ids of the higher-ranked neighbours, rows laid
-//                       out in old-id row order (a stream compaction of CSR)
+//                       out in union-id row order (a stream compaction of CSR)
 //   dag_rng[n]          (begin, end) of row x of the DAG, indexed by rank id
-//   eid[nnz]            for every CSR entry, the DAG position of its edge
+//   eid[nnz]            for every CSR entry of a TR graph, the DAG position of its edge
 //   del[m/32]           deletion bitmap over DAG positions
 #include "slim_internal.h"
 
@@ -252,26 +253,121 @@ void degree_rank(const int64_t* row_off, uint64_t n, int passes, uint32_t* ka, u
   *order_out = order;
 }
 
+// --------------------------------------------------------- small writes
+// Copies up to 256 bytes of host data to device memory as a kernel argument,
+// so that a call can set up its descriptors without a host-to-device copy
+// (and stays capturable in a HIP graph).
+struct Blob {
+  uint32_t w[64];
+};
+
+__global__ void k_put(uint32_t* dst, Blob b, uint32_t words) {
+  if (threadIdx.x < words) dst[threadIdx.x] = b.w[threadIdx.x];
+}
+
+void put_bytes(void* dst, const void* src, uint32_t bytes, hipStream_t s) {
+  Blob b{};
+  __builtin_memcpy(b.w, src, bytes);
+  hipLaunchKernelGGL(k_put, dim3(1), dim3(64), 0, s, static_cast<uint32_t*>(dst), b,
+                     (bytes + 3) / 4);
+}
+
 // ------------------------------------------------------ CSR tile machinery
-// Tile t holds CSR entries [t*kTile, (t+1)*kTile).  tile_lo[t] is the first
-// row whose start offset is >= t*kTile, so tile t "owns" the row starts of
-// rows [tile_lo[t], tile_lo[t+1]).
-__global__ void k_tile_lo(const int64_t* row_off, uint64_t n, uint64_t nnz, uint64_t ntiles,
-                          uint64_t tile, uint32_t* tile_lo) {
-  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t <= ntiles;
-       t += (uint64_t)gridDim.x * blockDim.x) {
-    int64_t j = (int64_t)(t * tile);
-    if ((uint64_t)j > nnz) j = (int64_t)nnz;
-    uint64_t lo = 0, hi = n;  // first r in [0,n] with row_off[r] >= j
-    while (lo < hi) {
-      uint64_t mid = (lo + hi) >> 1;
-      if (row_off[mid] < j)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    tile_lo[t] = (uint32_t)lo;
+// Last graph g with tile0[g] <= t (tile0 is non-decreasing; graphs without
+// tiles are skipped over).
+__device__ __forceinline__ uint32_t graph_of_tile(const uint64_t* tile0, uint32_t count,
+                                                  uint64_t t) {
+  uint32_t lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (tile0[mid] <= t)
+      lo = mid;
+    else
+      hi = mid;
   }
+  return lo;
+}
+
+// First union row r in [vb, ve] with row_off[r] >= j.
+__device__ __forceinline__ uint32_t first_row_at(const int64_t* row_off, uint64_t vb,
+                                                 uint64_t ve, int64_t j) {
+  uint64_t lo = vb, hi = ve;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (row_off[mid] < j)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (uint32_t)lo;
+}
+
+__global__ void k_tile_recs(const int64_t* row_off, const GDesc* gd, const uint64_t* tile0,
+                            uint32_t count, uint64_t ntiles, uint64_t tile, TileRec* recs) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ntiles;
+       t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t g = graph_of_tile(tile0, count, t);
+    const GDesc& G = gd[g];
+    const uint64_t end = G.eb + G.ne, ve = G.vb + G.nv;
+    const int64_t j0 = (int64_t)(G.eb + (t - tile0[g]) * tile);
+    const uint64_t left = end > (uint64_t)j0 ? end - (uint64_t)j0 : 0;
+    const uint32_t span = (uint32_t)(left < tile ? left : tile);
+    const bool last = t + 1 == tile0[g + 1];
+    TileRec R;
+    R.j0 = j0;
+    R.span = span;
+    R.g = g;
+    R.lo = first_row_at(row_off, G.vb, ve, j0);
+    R.hi = last ? (uint32_t)ve : first_row_at(row_off, G.vb, ve, j0 + span);
+    R.last = last ? 1u : 0u;
+    R.pad = 0;
+    recs[t] = R;
+  }
+}
+
+void tile_recs(const int64_t* row_off, const GDesc* gd, const uint64_t* tile0, uint32_t count,
+               uint64_t ntiles, uint64_t tile, TileRec* recs, hipStream_t s) {
+  if (ntiles)
+    hipLaunchKernelGGL(k_tile_recs, dim3(grid_for(ntiles)), dim3(kBlock), 0, s, row_off, gd,
+                       tile0, count, ntiles, tile, recs);
+}
+
+// Union CSR of a set: block-sized chunks of each graph's row offsets
+// (shifted by the graph's first entry) and columns (shifted by its first
+// vertex).
+__global__ __launch_bounds__(kBlock) void k_gather(const GDesc* gd, uint32_t count,
+                                                   const uint64_t* vtile0,
+                                                   const uint64_t* etile0, uint64_t nvt,
+                                                   uint64_t net, uint64_t N, uint64_t NNZ,
+                                                   int64_t* urow, uint32_t* ucol) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) urow[N] = (int64_t)NNZ;
+  for (uint64_t t = blockIdx.x; t < nvt + net; t += gridDim.x) {
+    const bool vert = t < nvt;
+    const uint64_t tt = vert ? t : t - nvt;
+    const uint64_t* pre = vert ? vtile0 : etile0;
+    const uint32_t g = graph_of_tile(pre, count, tt);
+    const GDesc& G = gd[g];
+    const uint64_t i0 = (tt - pre[g]) * kTile;
+    if (vert) {
+      const uint64_t i1 = i0 + kTile < G.nv ? i0 + kTile : G.nv;
+      for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBlock)
+        urow[G.vb + i] = G.in_row[i] + (int64_t)G.eb;
+    } else {
+      const uint64_t i1 = i0 + kTile < G.ne ? i0 + kTile : G.ne;
+      const uint32_t vb = (uint32_t)G.vb;
+      for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBlock) ucol[G.eb + i] = G.in_col[i] + vb;
+    }
+  }
+}
+
+void gather(const GDesc* gd, uint32_t count, const uint64_t* vtile0, const uint64_t* etile0,
+            uint64_t nvt, uint64_t net, uint64_t N, uint64_t NNZ, int64_t* urow, uint32_t* ucol,
+            hipStream_t s) {
+  uint64_t blocks = nvt + net;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(kBlock), 0, s, gd, count, vtile0,
+                     etile0, nvt, net, N, NNZ, urow, ucol);
 }
 
 struct TileRows {
@@ -315,63 +411,68 @@ __device__ __forceinline__ uint32_t tile_row_of(const TileRows& L, int i) {
 }
 
 // ------------------------------------------------ flag stream compaction
-// Policies decide per CSR entry j (row r) whether it is kept and what is
-// written; kept entries keep their CSR order, so rows stay sorted.
+// Policies decide per CSR entry j (union row r) whether it is kept and what
+// is written; kept entries keep their CSR order, so rows stay sorted.  A
+// policy's Ctx holds what it needs of the tile's graph.
 struct OrientPolicy {  // keep (r,c) iff rank(c) > rank(r); write rank(c)
-  static constexpr bool kNeedRows = true;
   const uint32_t* col;
   const uint32_t* rank;
-  __device__ bool flag(uint64_t j, uint32_t r) const { return rank[col[j]] > rank[r]; }
-  __device__ uint32_t value(uint64_t j) const { return rank[col[j]]; }
-  __device__ void kept(uint64_t, uint64_t) const {}
+  struct Ctx {};
+  __device__ Ctx ctx(const GDesc&) const { return {}; }
+  __device__ bool needs_rows(const GDesc&) const { return true; }
+  __device__ bool flag(const Ctx&, uint64_t j, uint32_t r) const {
+    return rank[col[j]] > rank[r];
+  }
+  __device__ uint32_t value(const Ctx&, uint64_t j) const { return rank[col[j]]; }
 };
 
-struct KeepPolicy {  // TR output: keep (r,c) iff its edge is not marked deleted
-  static constexpr bool kNeedRows = false;
+// Output of a compression job, per graph: a TR graph keeps (r,c) iff its
+// edge is not marked deleted; an ES graph keeps {a<b} (local ids) iff
+// Philox(a,b,0,1) word 0 >= thr.  Written values are local ids.
+struct OutPolicy {
   const uint32_t* col;
   const uint32_t* eid;
   const uint32_t* del;
   uint64_t m;
-  __device__ bool flag(uint64_t j, uint32_t) const {
+  struct Ctx {
+    uint64_t thr;
+    uint32_t vb, k0, k1, es;
+  };
+  __device__ Ctx ctx(const GDesc& G) const {
+    return Ctx{G.thr, (uint32_t)G.vb, G.k0, G.k1, G.op == SLIM_OP_ES ? 1u : 0u};
+  }
+  __device__ bool needs_rows(const GDesc& G) const { return G.op == SLIM_OP_ES; }
+  __device__ bool flag(const Ctx& x, uint64_t j, uint32_t r) const {
+    if (x.es) {
+      const uint32_t c = col[j] - x.vb, rl = r - x.vb;
+      const uint32_t a = c < rl ? c : rl, b = c < rl ? rl : c;
+      uint32_t w0, w1;
+      philox_w01(a, b, 0u, 1u, x.k0, x.k1, w0, w1);
+      return !((uint64_t)w0 < x.thr);
+    }
     const uint32_t e = eid[j];
     return e >= m || !bit_get(del, e);  // e >= m only for inputs breaking the contract
   }
-  __device__ uint32_t value(uint64_t j) const { return col[j]; }
-  __device__ void kept(uint64_t, uint64_t) const {}
-};
-
-struct SamplePolicy {  // ES output: keep {a<b} iff Philox(a,b,0,1).w0 >= thr
-  static constexpr bool kNeedRows = true;
-  const uint32_t* col;
-  uint64_t thr;
-  uint32_t k0, k1;
-  __device__ bool flag(uint64_t j, uint32_t r) const {
-    const uint32_t c = col[j];
-    const uint32_t a = c < r ? c : r, b = c < r ? r : c;
-    uint32_t w0, w1;
-    philox_w01(a, b, 0u, 1u, k0, k1, w0, w1);
-    return !((uint64_t)w0 < thr);
-  }
-  __device__ uint32_t value(uint64_t j) const { return col[j]; }
-  __device__ void kept(uint64_t, uint64_t) const {}
+  __device__ uint32_t value(const Ctx& x, uint64_t j) const { return col[j] - x.vb; }
 };
 
 template <class P>
 __global__ __launch_bounds__(kBlock) void k_compact_count(P p, const int64_t* row_off,
-                                                          const uint32_t* tile_lo, uint64_t nnz,
+                                                          const GDesc* gd, const TileRec* recs,
                                                           uint32_t* tile_cnt) {
   __shared__ TileRows L;
   __shared__ uint32_t wsum[kWavesPerBlock];
-  const uint64_t t = blockIdx.x;
-  const int64_t j0 = (int64_t)(t * kTile);
+  const TileRec R = recs[blockIdx.x];
+  const GDesc& G = gd[R.g];
+  const typename P::Ctx x = p.ctx(G);
+  const bool rows = p.needs_rows(G);
   const int w = threadIdx.x / kWave, lane = lane_id();
-  if (P::kNeedRows) tile_rows(row_off, j0, tile_lo[t], tile_lo[t + 1], L);
+  if (rows) tile_rows(row_off, R.j0, R.lo, R.hi, L);
   uint32_t cnt = 0;
   for (int c = w; c < kChunks; c += kWavesPerBlock) {
     const int i = c * kWave + lane;
-    const uint64_t j = (uint64_t)j0 + i;
     bool f = false;
-    if (j < nnz) f = p.flag(j, P::kNeedRows ? tile_row_of(L, i) : 0u);
+    if ((uint32_t)i < R.span) f = p.flag(x, (uint64_t)R.j0 + i, rows ? tile_row_of(L, i) : 0u);
     cnt += __popcll(__ballot(f));
   }
   if (lane == 0) wsum[w] = cnt;
@@ -379,31 +480,35 @@ __global__ __launch_bounds__(kBlock) void k_compact_count(P p, const int64_t* ro
   if (threadIdx.x == 0) {
     uint32_t s = 0;
     for (int i = 0; i < kWavesPerBlock; ++i) s += wsum[i];
-    tile_cnt[t] = s;
+    tile_cnt[blockIdx.x] = s;
   }
 }
 
+// Kept entries go to the tile's graph's output at (scan of the set) minus
+// (scan at the graph's first tile); the tile also writes the row starts it
+// owns and, if it is the graph's last tile, the end offset.
 template <class P, typename OffT>
-__global__ __launch_bounds__(kBlock) void k_compact_scatter(
-    P p, const int64_t* row_off, const uint32_t* tile_lo, uint64_t n, uint64_t nnz,
-    uint64_t ntiles, const uint64_t* tile_base, uint32_t* out, uint64_t out_cap,
-    OffT* row_start) {
+__global__ __launch_bounds__(kBlock) void k_compact_scatter(P p, const int64_t* row_off,
+                                                            const GDesc* gd,
+                                                            const uint64_t* tile0,
+                                                            const TileRec* recs,
+                                                            const uint64_t* tile_base) {
   __shared__ TileRows L;
   __shared__ uint64_t cmask[kChunks];
-  __shared__ uint32_t cbase[kChunks];
-  const uint64_t t = blockIdx.x;
-  const int64_t j0 = (int64_t)(t * kTile);
+  __shared__ uint32_t cbase[kChunks + 1];
+  const TileRec R = recs[blockIdx.x];
+  const GDesc& G = gd[R.g];
+  const typename P::Ctx x = p.ctx(G);
+  const bool rows = p.needs_rows(G);
   const int w = threadIdx.x / kWave, lane = lane_id();
-  const uint32_t lo = tile_lo[t], hi = tile_lo[t + 1];
-  if (P::kNeedRows) tile_rows(row_off, j0, lo, hi, L);
+  if (rows) tile_rows(row_off, R.j0, R.lo, R.hi, L);
   uint32_t fbits = 0;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     const int c = w + k * kWavesPerBlock;
     const int i = c * kWave + lane;
-    const uint64_t j = (uint64_t)j0 + i;
     bool f = false;
-    if (j < nnz) f = p.flag(j, P::kNeedRows ? tile_row_of(L, i) : 0u);
+    if ((uint32_t)i < R.span) f = p.flag(x, (uint64_t)R.j0 + i, rows ? tile_row_of(L, i) : 0u);
     const uint64_t m = __ballot(f);
     if (lane == 0) cmask[c] = m;
     if (f) fbits |= 1u << k;
@@ -413,64 +518,56 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(
     const uint32_t v = __popcll(cmask[lane]);
     const uint64_t incl = wave_incl_sum64(v);
     cbase[lane] = (uint32_t)(incl - v);
+    if (lane == kWave - 1) cbase[kChunks] = (uint32_t)incl;
   }
   __syncthreads();
-  const uint64_t base = tile_base[t];
+  const uint64_t cap = G.cap;
+  uint32_t* out = G.out_col;
+  OffT* rstart = static_cast<OffT*>(G.out_row);
+  const uint64_t base = tile_base[blockIdx.x] - tile_base[tile0[R.g]];
   const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     if (fbits & (1u << k)) {
       const int c = w + k * kWavesPerBlock;
-      const uint64_t j = (uint64_t)j0 + c * kWave + lane;
+      const uint64_t j = (uint64_t)R.j0 + c * kWave + lane;
       const uint64_t pos = base + cbase[c] + __popcll(cmask[c] & lt);
-      if (pos < out_cap) {  // always true for inputs that meet the CSR contract
-        out[pos] = p.value(j);
-        p.kept(j, pos);
-      }
+      if (pos < cap) out[pos] = p.value(x, j);  // always true for inputs that meet the contract
     }
   }
-  for (uint32_t r = lo + threadIdx.x; r < hi; r += kBlock) {
-    const int64_t s = row_off[r] - j0;
-    const int c = (int)(s >> 6);
-    const uint64_t below = (uint64_t(1) << (s & 63)) - 1;
-    const uint64_t v = base + cbase[c] + __popcll(cmask[c] & below);
-    row_start[r] = (OffT)(v < out_cap ? v : out_cap);
+  const uint32_t total = cbase[kChunks];
+  for (uint32_t r = R.lo + threadIdx.x; r < R.hi; r += kBlock) {
+    const int64_t s = row_off[r] - R.j0;
+    uint64_t v = base + total;
+    if (s >= 0 && s < (int64_t)R.span) {
+      const int c = (int)(s >> 6);
+      v = base + cbase[c] + __popcll(cmask[c] & ((uint64_t(1) << (s & 63)) - 1));
+    }
+    rstart[r - G.vb] = (OffT)(v < cap ? v : cap);
   }
-  if (t + 1 == ntiles) {
-    uint64_t total = base + cbase[kChunks - 1] + __popcll(cmask[kChunks - 1]);
-    if (total > out_cap) total = out_cap;
-    for (uint64_t r = hi + threadIdx.x; r <= n; r += kBlock) row_start[r] = (OffT)total;
+  if (R.last && threadIdx.x == 0) {
+    const uint64_t v = base + total;
+    rstart[G.nv] = (OffT)(v < cap ? v : cap);
   }
 }
 
 template <class P, typename OffT>
-void compact(const P& p, const int64_t* row_off, const uint32_t* tile_lo, uint64_t n,
-             uint64_t nnz, uint64_t ntiles, uint32_t* tile_cnt, uint64_t* tile_base,
-             uint64_t* scan_tmp, uint32_t* out, uint64_t out_cap, OffT* row_start,
-             hipStream_t s) {
+void compact(const P& p, const int64_t* row_off, const GDesc* gd, const uint64_t* tile0,
+             const TileRec* recs, uint64_t ntiles, uint32_t* tile_cnt, uint64_t* tile_base,
+             uint64_t* scan_tmp, hipStream_t s) {
   hipLaunchKernelGGL(k_compact_count<P>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, p, row_off,
-                     tile_lo, nnz, tile_cnt);
+                     gd, recs, tile_cnt);
   scan_excl<uint32_t>(tile_cnt, ntiles, tile_base, scan_tmp, s);
   hipLaunchKernelGGL((k_compact_scatter<P, OffT>), dim3((unsigned)ntiles), dim3(kBlock), 0, s, p,
-                     row_off, tile_lo, n, nnz, ntiles, (const uint64_t*)tile_base, out, out_cap,
-                     row_start);
+                     row_off, gd, tile0, recs, (const uint64_t*)tile_base);
 }
 
-void tile_lo_build(const int64_t* row_off, uint64_t n, uint64_t nnz, uint64_t ntiles,
-                   uint32_t* tile_lo, hipStream_t s, uint64_t tile) {
-  hipLaunchKernelGGL(k_tile_lo, dim3(grid_for(ntiles + 1)), dim3(kBlock), 0, s, row_off, n, nnz,
-                     ntiles, tile, tile_lo);
-}
-
-// DAG: dag_col = rank ids of forward entries; eid for forward entries.
-void orient(const int64_t* row_off, const uint32_t* col, const uint32_t* rank, uint64_t n,
-            uint64_t nnz, uint64_t ntiles, const uint32_t* tile_lo, uint32_t* tile_cnt,
-            uint64_t* tile_base, uint64_t* scan_tmp, uint32_t* dag_col, uint32_t* eid,
-            uint32_t* fstart, hipStream_t s) {
-  (void)eid;  // edge ids are assigned after the row sort, by the triangle kernel
+void orient(const int64_t* row_off, const uint32_t* col, const uint32_t* rank,
+            const GDesc* gd_union, const uint64_t* tile0, const TileRec* recs, uint64_t ntiles,
+            uint32_t* tile_cnt, uint64_t* tile_base, uint64_t* scan_tmp, hipStream_t s) {
   OrientPolicy p{col, rank};
-  compact<OrientPolicy, uint32_t>(p, row_off, tile_lo, n, nnz, ntiles, tile_cnt, tile_base,
-                                  scan_tmp, dag_col, nnz / 2, fstart, s);
+  compact<OrientPolicy, uint32_t>(p, row_off, gd_union, tile0, recs, ntiles, tile_cnt, tile_base,
+                                  scan_tmp, s);
 }
 
 __global__ void k_dag_rng(const uint32_t* order, const uint32_t* fstart, uint64_t n,
@@ -488,41 +585,41 @@ void dag_ranges(const uint32_t* order, const uint32_t* fstart, uint64_t n, uint2
                      dag_rng);
 }
 
-void compact_tr(const int64_t* row_off, const uint32_t* col, const uint32_t* eid,
-                const uint32_t* del, uint64_t n, uint64_t nnz, uint64_t ntiles,
-                const uint32_t* tile_lo, uint32_t* tile_cnt, uint64_t* tile_base,
-                uint64_t* scan_tmp, uint32_t* out_col, int64_t* out_row_off, hipStream_t s) {
-  KeepPolicy p{col, eid, del, nnz / 2};
-  compact<KeepPolicy, int64_t>(p, row_off, tile_lo, n, nnz, ntiles, tile_cnt, tile_base,
-                               scan_tmp, out_col, nnz, out_row_off, s);
-}
-
-void compact_es(const int64_t* row_off, const uint32_t* col, uint64_t thr, uint64_t seed,
-                uint64_t n, uint64_t nnz, uint64_t ntiles, const uint32_t* tile_lo,
-                uint32_t* tile_cnt, uint64_t* tile_base, uint64_t* scan_tmp, uint32_t* out_col,
-                int64_t* out_row_off, hipStream_t s) {
-  SamplePolicy p{col, thr, (uint32_t)seed, (uint32_t)(seed >> 32)};
-  compact<SamplePolicy, int64_t>(p, row_off, tile_lo, n, nnz, ntiles, tile_cnt, tile_base,
-                                 scan_tmp, out_col, nnz, out_row_off, s);
+void compact_out(const int64_t* row_off, const uint32_t* col, const uint32_t* eid,
+                 const uint32_t* del, uint64_t m, const GDesc* gd, const uint64_t* tile0,
+                 const TileRec* recs, uint64_t ntiles, uint32_t* tile_cnt, uint64_t* tile_base,
+                 uint64_t* scan_tmp, hipStream_t s) {
+  OutPolicy p{col, eid, del, m};
+  compact<OutPolicy, int64_t>(p, row_off, gd, tile0, recs, ntiles, tile_cnt, tile_base,
+                              scan_tmp, s);
 }
 
 // --------------------------------------------------------------- stats
-__global__ void k_stats(uint64_t n, uint64_t nnz, const uint64_t* counters,
-                        const uint64_t* kept, slim_stats_t* st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const uint64_t m = nnz / 2, m_out = (kept ? *kept : nnz) / 2;
-    st->n = n;
-    st->m_in = m;
-    st->triangles = counters ? counters[0] : 0;
-    st->selected = counters ? counters[1] : 0;
-    st->deleted = m - m_out;
-    st->m_out = m_out;
+__global__ void k_stats(const GDesc* gd, uint32_t count, const uint64_t* tile0,
+                        const uint64_t* counters, const uint64_t* tile_base) {
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < count;
+       g += gridDim.x * blockDim.x) {
+    const GDesc& G = gd[g];
+    if (!G.stats) continue;
+    const uint64_t m = G.ne / 2;
+    const uint64_t m_out = (tile_base[tile0[g + 1]] - tile_base[tile0[g]]) / 2;
+    const bool tr = G.op == SLIM_OP_TR && counters;
+    slim_stats_t st;
+    st.n = G.nv;
+    st.m_in = m;
+    st.triangles = tr ? counters[2 * g] : 0;
+    st.selected = tr ? counters[2 * g + 1] : 0;
+    st.deleted = m - m_out;
+    st.m_out = m_out;
+    *G.stats = st;
   }
 }
 
-void write_stats(uint64_t n, uint64_t nnz, const uint64_t* counters, const uint64_t* kept,
-                 slim_stats_t* st, hipStream_t s) {
-  if (st) hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, s, n, nnz, counters, kept, st);
+void write_stats(const GDesc* gd, uint32_t count, const uint64_t* tile0,
+                 const uint64_t* counters, const uint64_t* tile_base, hipStream_t s) {
+  if (count)
+    hipLaunchKernelGGL(k_stats, dim3(grid_for(count)), dim3(kBlock), 0, s, gd, count, tile0,
+                       counters, tile_base);
 }
 
 // ------------------------------------------------------------ validation
@@ -541,17 +638,14 @@ __global__ void k_validate_offsets(const int64_t* row_off, uint64_t n, uint64_t 
 
 __global__ __launch_bounds__(kBlock) void k_validate_entries(const int64_t* row_off,
                                                              const uint32_t* col, uint64_t n,
-                                                             uint64_t nnz,
-                                                             const uint32_t* tile_lo,
+                                                             const TileRec* recs,
                                                              uint32_t* err) {
   __shared__ TileRows L;
-  const uint64_t t = blockIdx.x;
-  const int64_t j0 = (int64_t)(t * kTile);
-  tile_rows(row_off, j0, tile_lo[t], tile_lo[t + 1], L);
+  const TileRec R = recs[blockIdx.x];
+  tile_rows(row_off, R.j0, R.lo, R.hi, L);
   uint32_t e = 0;
-  for (int i = threadIdx.x; i < kTile; i += kBlock) {
-    const uint64_t j = (uint64_t)j0 + i;
-    if (j >= nnz) break;
+  for (int i = threadIdx.x; (uint32_t)i < R.span; i += kBlock) {
+    const uint64_t j = (uint64_t)R.j0 + i;
     const uint32_t r = tile_row_of(L, i);
     const uint32_t c = col[j];
     if ((uint64_t)c >= n) {
@@ -579,10 +673,10 @@ void validate_offsets(const int64_t* row_off, uint64_t n, uint64_t nnz, uint32_t
                      nnz, err);
 }
 
-void validate_entries(const int64_t* row_off, const uint32_t* col, uint64_t n, uint64_t nnz,
-                      uint64_t ntiles, const uint32_t* tile_lo, uint32_t* err, hipStream_t s) {
+void validate_entries(const int64_t* row_off, const uint32_t* col, uint64_t n,
+                      const TileRec* recs, uint64_t ntiles, uint32_t* err, hipStream_t s) {
   hipLaunchKernelGGL(k_validate_entries, dim3((unsigned)ntiles), dim3(kBlock), 0, s, row_off,
-                     col, n, nnz, tile_lo, err);
+                     col, n, recs, err);
 }
 
 }  // namespace slim

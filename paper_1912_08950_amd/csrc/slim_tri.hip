@@ -135,6 +135,8 @@ struct TriCtx {
   int64_t j0;
   uint32_t D0;    // first DAG position of the hashed range
   uint32_t hlen;  // number of hashed entries
+  uint64_t thr;   // the tile's graph: selection threshold, Philox key, first vertex
+  uint32_t k0, k1, vb;
   uint64_t n_tri, n_sel;
 };
 
@@ -198,7 +200,7 @@ __device__ void tri_forward_eids(TriCtx& C, TriSmem& S, uint32_t ia, uint32_t ib
 // Hash, select and mark the queued hits q[head .. head + cnt) (cnt <= 64);
 // one lane per hit.  Returns 1 in lanes whose triangle was selected.
 __device__ __forceinline__ uint32_t tri_drain(uint32_t* del, uint64_t thr, uint32_t k0,
-                                                        uint32_t k1, TriSmem* Sp,
+                                                        uint32_t k1, uint32_t vb, TriSmem* Sp,
                                                         const uint2* q, uint32_t head,
                                                         uint32_t cnt, uint32_t D0) {
   TriSmem& S = *Sp;
@@ -212,9 +214,9 @@ __device__ __forceinline__ uint32_t tri_drain(uint32_t* del, uint64_t thr, uint3
     const uint32_t ow = S.xold[qpos];
     const uint32_t c = ie.z, u0 = ie.w;
     uint32_t t0 = c, t1 = u0, t2 = ow;
-    sort3(t0, t1, t2);
+    sort3(t0, t1, t2);  // union ids of one graph: the order of its local ids
     uint32_t w0, w1;
-    philox_w01(t0, t1, t2, 0u, k0, k1, w0, w1);
+    philox_w01(t0 - vb, t1 - vb, t2 - vb, 0u, k0, k1, w0, w1);
     if ((uint64_t)w0 < thr) {
       sel = 1;
       const uint32_t kk = __umulhi(w1, 3u);  // 0:{t0,t1} 1:{t0,t2} 2:{t1,t2}
@@ -379,7 +381,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
         qcnt += __popcll(bal);
         if (qcnt >= (uint32_t)kWave) {
           wave_sync();
-          C.n_sel += tri_drain(C.a.del, C.a.thr, C.a.k0, C.a.k1, &S, q, qhead, kWave, C.D0);
+          C.n_sel += tri_drain(C.a.del, C.thr, C.k0, C.k1, C.vb, &S, q, qhead, kWave, C.D0);
           C.n_tri += 1;
           qhead = (qhead + kWave) % kQ;
           qcnt -= kWave;
@@ -389,7 +391,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
   }
   if (qcnt) {
     wave_sync();
-    C.n_sel += tri_drain(C.a.del, C.a.thr, C.a.k0, C.a.k1, &S, q, qhead, qcnt, C.D0);
+    C.n_sel += tri_drain(C.a.del, C.thr, C.k0, C.k1, C.vb, &S, q, qhead, qcnt, C.D0);
     C.n_tri += lane < qcnt ? 1 : 0;
   }
   __syncthreads();
@@ -399,29 +401,67 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
   __syncthreads();
 }
 
+// Adds the block's triangle and selection counts to graph g's counters.
+__device__ void tri_flush_counts(TriCtx& C, TriSmem& S, uint32_t g) {
+  const int tid = threadIdx.x, w = tid / kWave;
+  const uint64_t s0 = wave_sum64(C.n_tri), s1 = wave_sum64(C.n_sel);
+  if (lane_id() == 0) {
+    S.red[0][w] = s0;
+    S.red[1][w] = s1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t t0 = 0, t1 = 0;
+    for (int i = 0; i < kTW; ++i) {
+      t0 += S.red[0][i];
+      t1 += S.red[1][i];
+    }
+    if (t0) atomicAdd((unsigned long long*)&C.a.counters[2 * g], (unsigned long long)t0);
+    if (t1) atomicAdd((unsigned long long*)&C.a.counters[2 * g + 1], (unsigned long long)t1);
+  }
+  __syncthreads();
+  C.n_tri = 0;
+  C.n_sel = 0;
+}
+
+// Persistent blocks take tiles in increasing order from a counter, so the
+// graph of a block's tiles never decreases: counts are flushed when it
+// changes and at the end.
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k_triangles(
-    TriArgs a, const uint32_t* tlo,
-                                                   uint64_t ntiles, uint32_t* tile_ctr,
-                                                   uint32_t cap) {
+    TriArgs a, uint32_t* tile_ctr, uint32_t cap) {
   __shared__ TriSmem S;
   TriCtx C;
   C.a = a;
   C.cap = cap;
   C.n_tri = 0;
   C.n_sel = 0;
+  C.thr = 0;
+  C.k0 = C.k1 = C.vb = 0;
   const int tid = threadIdx.x, w = tid / kWave;
   const uint32_t lane = lane_id();
-  const uint64_t nnz = a.nnz;
+  const uint64_t ntiles = a.ntiles;
+  uint32_t gcur = 0xffffffffu;
   for (;;) {
     if (tid == 0) S.bcast[0] = atomicAdd(tile_ctr, 1u);
     __syncthreads();
     const uint64_t t = S.bcast[0];
     __syncthreads();
     if (t >= ntiles) break;
-    const int64_t j0 = (int64_t)(t * kTT);
-    const uint32_t span = (uint32_t)((uint64_t)j0 + kTT <= nnz ? kTT : nnz - j0);
+    const TileRec R = a.recs[t];
+    if (R.span == 0) continue;  // a graph without edges
+    if (R.g != gcur) {
+      if (gcur != 0xffffffffu) tri_flush_counts(C, S, gcur);
+      gcur = R.g;
+      const GDesc& G = a.gd[gcur];
+      C.thr = G.thr;
+      C.k0 = G.k0;
+      C.k1 = G.k1;
+      C.vb = (uint32_t)G.vb;
+    }
+    const int64_t j0 = R.j0;
+    const uint32_t span = R.span;
     C.j0 = j0;
-    tri_tile_rows(a.row_off, j0, tlo[t], tlo[t + 1], S);
+    tri_tile_rows(a.row_off, j0, R.lo, R.hi, S);
     // ---- backward entries (the in-edges of the tile's rows), in CSR order
     uint32_t fb = 0;
     for (int k = 0; k < kTC / kTW; ++k) {
@@ -561,39 +601,20 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
       tri_flush_xbits(C, S);
     }
   }
-  // ---- counters
-  const uint64_t s0 = wave_sum64(C.n_tri), s1 = wave_sum64(C.n_sel);
-  if (lane == 0) {
-    S.red[0][w] = s0;
-    S.red[1][w] = s1;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint64_t t0 = 0, t1 = 0;
-    for (int i = 0; i < kTW; ++i) {
-      t0 += S.red[0][i];
-      t1 += S.red[1][i];
-    }
-    if (t0) atomicAdd((unsigned long long*)&a.counters[0], (unsigned long long)t0);
-    if (t1) atomicAdd((unsigned long long*)&a.counters[1], (unsigned long long)t1);
-  }
+  if (gcur != 0xffffffffu) tri_flush_counts(C, S, gcur);
 }
 
-uint64_t tri_tiles(uint64_t nnz) { return (nnz + kTT - 1) / kTT; }
-uint64_t tri_tile_entries() { return kTT; }
+uint64_t tri_tile_max() { return kTT; }
 
-void triangles(const TriArgs& a, const uint32_t* tlo, uint32_t* tile_ctr, int num_cu,
+void triangles(const TriArgs& a, uint32_t* tile_ctr, int num_cu, int blocks_per_cu, int chunk,
                hipStream_t s) {
-  const uint64_t ntiles = tri_tiles(a.nnz);
-  const Tuning& t = tuning();
-  uint64_t blocks = (uint64_t)num_cu * t.tri_blocks_per_cu;
-  if (blocks > ntiles) blocks = ntiles;
+  uint64_t blocks = (uint64_t)num_cu * blocks_per_cu;
+  if (blocks > a.ntiles) blocks = a.ntiles;
   if (blocks < 1) blocks = 1;
   fill_u32(tile_ctr, 1, 0, s);
-  uint32_t cap = (uint32_t)t.tri_chunk;
+  uint32_t cap = (uint32_t)chunk;
   if (cap > (uint32_t)kHashCap) cap = kHashCap;
-  hipLaunchKernelGGL(k_triangles, dim3((unsigned)blocks), dim3(kTB), 0, s, a, tlo, ntiles,
-                     tile_ctr, cap);
+  hipLaunchKernelGGL(k_triangles, dim3((unsigned)blocks), dim3(kTB), 0, s, a, tile_ctr, cap);
 }
 
 }  // namespace slim

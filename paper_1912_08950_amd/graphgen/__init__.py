@@ -12,6 +12,12 @@ graphs stand in for them):
 * ``rmat(scale, edge_factor, seed)`` -- R-MAT with a,b,c,d = .57,.19,.19,.05,
   edge_factor * 2^scale directed samples, ids through a seeded bijection of
   [0, 2^scale), symmetrized, self-loops and duplicates removed.
+* ``batch_mix(count, seed, ...)`` -- a mixed population of many graphs: half
+  G(n, q), half R-MAT, n log-uniform in [n_lo, n_hi], average degree d
+  uniform in [d_lo, d_hi].  An R-MAT member is drawn at scale ceil(log2 n)
+  with endpoints >= n dropped; its sample count d/2 * n * (2^scale / n)^2
+  makes up for the dropped samples, so its average degree is d before
+  duplicate removal.  ``mix_seed(base, i)`` derives the per-graph seeds.
 """
 from __future__ import annotations
 
@@ -189,3 +195,35 @@ def empty(n: int) -> CSR:
 
 def num_threads() -> int:
     return int(_load().sg_num_threads())
+
+
+def mix_seed(base: int, i: int) -> int:
+    """Per-item seed from a base seed: the SplitMix64 output function applied
+    to base + (i + 1) * 0x9E3779B97F4A7C15 (mod 2^64)."""
+    m = (1 << 64) - 1
+    z = (int(base) + (int(i) + 1) * 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def batch_mix(count: int, seed: int, n_lo: int = 1000, n_hi: int = 200000, d_lo: float = 4.0,
+              d_hi: float = 64.0):
+    """`count` graphs, even indices G(n, q) and odd indices R-MAT, with n
+    log-uniform in [n_lo, n_hi] and average degree uniform in [d_lo, d_hi]
+    (parameters from numpy's PCG64 seeded with `seed`; graph i's generator
+    seed is mix_seed(seed, i)).  Returns a list of CSR."""
+    rng = np.random.default_rng(seed)
+    ns = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count)).astype(np.int64)
+    ds = rng.uniform(d_lo, d_hi, count)
+    out = []
+    for i in range(count):
+        n, d, s = int(max(ns[i], 2)), float(ds[i]), mix_seed(seed, i) & 0x7FFFFFFFFFFFFFFF
+        if i % 2 == 0:
+            g = er(n, d, s)
+        else:
+            scale = max(1, int(np.ceil(np.log2(n))))
+            samples = int(round(d / 2 * n * ((1 << scale) / n) ** 2))
+            g = rmat(scale, d / 2, s, n=n, samples=samples)
+        out.append(g)
+    return out

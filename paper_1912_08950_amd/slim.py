@@ -26,11 +26,23 @@ STAT_KEYS = ("n", "m_in", "triangles", "selected", "deleted", "m_out")
 # Exported symbols of libslim.so, in include/slim.h order.
 SYMBOLS = ("slim_last_error", "slim_strerror", "slim_version", "slim_load_csr",
            "slim_graph_free", "slim_workspace_size", "slim_triangle_reduce", "slim_edge_sample",
+           "slim_batch_create", "slim_batch_workspace_size", "slim_batch_run", "slim_batch_set",
+           "slim_batch_get", "slim_batch_tune", "slim_batch_free",
            "slim_tune_set", "slim_tune_get", "slim_profile_enable", "slim_profile_read")
 
 
 class Phase(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("ms", ctypes.c_float)]
+
+
+class JobParams(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("pad", ctypes.c_int32), ("p", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class Out(ctypes.Structure):
+    _fields_ = [("row_off", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("stats", ctypes.c_void_p)]
 
 
 class SlimError(RuntimeError):
@@ -60,6 +72,21 @@ def _bind(path: str = LIB_PATH):
     for fn in (lib.slim_triangle_reduce, lib.slim_edge_sample):
         fn.restype = i32
         fn.argtypes = [vp, dbl, u64, vp, u64, vp, vp, vp, vp]
+    lib.slim_batch_create.restype = i32
+    lib.slim_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(JobParams), u32,
+                                      ctypes.POINTER(vp)]
+    lib.slim_batch_workspace_size.restype = i32
+    lib.slim_batch_workspace_size.argtypes = [vp, ctypes.POINTER(u64)]
+    lib.slim_batch_run.restype = i32
+    lib.slim_batch_run.argtypes = [vp, vp, u64, ctypes.POINTER(Out), vp]
+    lib.slim_batch_set.restype = i32
+    lib.slim_batch_set.argtypes = [vp, ctypes.c_char_p, ctypes.c_int64]
+    lib.slim_batch_get.restype = i32
+    lib.slim_batch_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
+    lib.slim_batch_tune.restype = i32
+    lib.slim_batch_tune.argtypes = [vp, vp, u64, ctypes.POINTER(Out), ctypes.c_char_p, vp]
+    lib.slim_batch_free.restype = None
+    lib.slim_batch_free.argtypes = [vp]
     lib.slim_tune_set.restype = i32
     lib.slim_tune_set.argtypes = [ctypes.c_char_p, ctypes.c_int64]
     lib.slim_tune_get.restype = i32
@@ -216,3 +243,92 @@ def result_numpy(bufs: Buffers):
     col = bufs.out_col[:nnz_out].cpu().numpy().view(np.uint32)
     st = dict(zip(STAT_KEYS, (int(x) for x in bufs.stats.cpu().numpy())))
     return ro, col, st
+
+
+class Batch:
+    """Many (graph, op, p, seed) jobs run as one graph set (slim_batch_*).
+
+    ``jobs`` holds one ``(op, p, seed)`` per graph.  Output tensors for all
+    graphs are allocated here as three flat tensors sliced per graph
+    (``row_off``/``col``/``stats`` views), plus the workspace.
+    """
+
+    def __init__(self, graphs: list[Graph], jobs):
+        if len(graphs) != len(jobs) or not graphs:
+            raise ValueError("one job per graph, at least one graph")
+        self.graphs = list(graphs)
+        self.device = graphs[0].device
+        hs = (ctypes.c_void_p * len(graphs))(*[g._h.value for g in graphs])
+        js = (JobParams * len(jobs))(*[JobParams(int(op), 0, float(p), int(seed) & (2**64 - 1))
+                                       for op, p, seed in jobs])
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.slim_batch_create(hs, js, len(graphs), ctypes.byref(h)))
+        self._h = h
+        b = ctypes.c_uint64(0)
+        _check(_lib.slim_batch_workspace_size(h, ctypes.byref(b)))
+        self.ws_bytes = int(b.value)
+        dev = self.device
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
+        ns = np.array([g.n for g in graphs], dtype=np.int64)
+        nnzs = np.array([g.nnz for g in graphs], dtype=np.int64)
+        self.ro_base = np.concatenate([[0], np.cumsum(ns + 1)])
+        self.col_base = np.concatenate([[0], np.cumsum(nnzs)])
+        self.row_off_all = torch.empty(int(self.ro_base[-1]), dtype=torch.int64, device=dev)
+        self.col_all = torch.empty(max(int(self.col_base[-1]), 1), dtype=torch.int32, device=dev)
+        self.stats_all = torch.zeros((len(graphs), len(STAT_KEYS)), dtype=torch.int64, device=dev)
+        rp, cp, sp = (self.row_off_all.data_ptr(), self.col_all.data_ptr(),
+                      self.stats_all.data_ptr())
+        self._outs = (Out * len(graphs))(*[
+            Out(rp + 8 * int(self.ro_base[i]), cp + 4 * int(self.col_base[i]) if nnzs[i] else None,
+                sp + 8 * len(STAT_KEYS) * i) for i in range(len(graphs))])
+
+    def __len__(self):
+        return len(self.graphs)
+
+    def set(self, key: str, value: int):
+        _check(_lib.slim_batch_set(self._h, key.encode(), int(value)))
+
+    def get(self, key: str) -> int:
+        v = ctypes.c_int64(0)
+        _check(_lib.slim_batch_get(self._h, key.encode(), ctypes.byref(v)))
+        return int(v.value)
+
+    def run(self, stream=None):
+        """Enqueue every job (results valid after stream sync)."""
+        with torch.cuda.device(self.device):
+            _check(_lib.slim_batch_run(self._h, self.ws.data_ptr(), self.ws_bytes, self._outs,
+                                       _stream_handle(stream, self.device)))
+
+    def tune(self, cache_path: str | None = None, stream=None):
+        """Autotune the batch's knobs (runs it several times; synchronises)."""
+        with torch.cuda.device(self.device):
+            _check(_lib.slim_batch_tune(self._h, self.ws.data_ptr(), self.ws_bytes, self._outs,
+                                        cache_path.encode() if cache_path else None,
+                                        _stream_handle(stream, self.device)))
+
+    def stats(self) -> list[dict]:
+        torch.cuda.synchronize(self.device)
+        return [dict(zip(STAT_KEYS, (int(x) for x in row))) for row in self.stats_all.cpu().numpy()]
+
+    def result_numpy(self, i: int):
+        """Synchronise and copy graph i's result: (row_off, col, stats dict)."""
+        torch.cuda.synchronize(self.device)
+        a, b = int(self.ro_base[i]), int(self.ro_base[i + 1])
+        ro = self.row_off_all[a:b].cpu().numpy()
+        c0 = int(self.col_base[i])
+        col = self.col_all[c0:c0 + int(ro[-1])].cpu().numpy().view(np.uint32)
+        st = dict(zip(STAT_KEYS, (int(x) for x in self.stats_all[i].cpu().numpy())))
+        return ro, col, st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            torch.cuda.synchronize(self.device)
+            _lib.slim_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,157 @@
+"""GPU parity of batches (slim_batch_*): every job of a batch must produce
+exactly what the single-graph call produces for the same (graph, op, p,
+seed) -- and so what the CPU oracle produces -- whatever the batch's mix of
+sizes, operations, parameters and knobs, on first capture and on replays."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1912_08950_amd import graphgen as gg
+from test_parity_gpu import SMALL, assert_same, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def slim(gpu):
+    from paper_1912_08950_amd import slim as s
+    return s
+
+
+def single(slim, dg, op, p, seed):
+    fn = slim.triangle_reduce if op == slim.OP_TR else slim.edge_sample
+    return slim.result_numpy(fn(dg, p, seed))
+
+
+def check_batch(slim, graphs, jobs, dgs=None, oracle_idx=None, knobs=None, use_graph=True,
+                runs=2):
+    dgs = dgs or [slim.Graph.from_csr(g) for g in graphs]
+    b = slim.Batch(dgs, jobs)
+    b.set("use_graph", 1 if use_graph else 0)
+    for k, v in (knobs or {}).items():
+        b.set(k, v)
+    want = [single(slim, dg, *job) for dg, job in zip(dgs, jobs)]
+    for r in range(runs):
+        b.run()
+        for i, w in enumerate(want):
+            assert_same(b.result_numpy(i), w, f"run {r} graph {i} {graphs[i].name} {jobs[i]}")
+    for i in (oracle_idx if oracle_idx is not None else range(len(graphs))):
+        op, p, seed = jobs[i]
+        assert_same(b.result_numpy(i), oracle_run(graphs[i], "tr" if op == slim.OP_TR else "es",
+                                                  p, seed), f"oracle graph {i}")
+    return b
+
+
+def test_batch_of_small_graphs_mixed_ops(slim):
+    """Every small fixture graph (empty, edgeless, single edge, hubs over
+    several tiles, ...) in one batch, TR and ES mixed, different p and seeds."""
+    graphs = [f() for f in SMALL.values()]
+    ps = (0.5, 0.0, 1.0, 0.2, 0.8)
+    jobs = [(slim.OP_TR if i % 3 else slim.OP_ES, ps[i % 5], 1000 + i) for i in range(len(graphs))]
+    check_batch(slim, graphs, jobs)
+
+
+def test_batch_same_graph_many_seeds(slim):
+    g = gg.er(2000, 16.0, 1)
+    dg = slim.Graph.from_csr(g)
+    jobs = [(slim.OP_TR, 0.5, s) for s in range(1, 33)] + [(slim.OP_ES, 0.5, s) for s in range(1, 9)]
+    check_batch(slim, [g] * len(jobs), jobs, dgs=[dg] * len(jobs), oracle_idx=[0, 7, 31, 32, 39])
+
+
+def test_batch_single_graph(slim):
+    g = gg.rmat(12, 16, 4)
+    check_batch(slim, [g], [(slim.OP_TR, 0.5, 3)])
+
+
+def test_batch_only_edgeless(slim):
+    graphs = [gg.empty(1), gg.empty(7), gg.empty(4100)]
+    check_batch(slim, graphs, [(slim.OP_TR, 0.5, 1), (slim.OP_ES, 0.5, 1), (slim.OP_TR, 1.0, 2)])
+
+
+def test_batch_only_es(slim):
+    graphs = [gg.er(3000, 10.0, 5), gg.rmat(11, 8, 2), gg.path(9)]
+    check_batch(slim, graphs, [(slim.OP_ES, 0.3, 1), (slim.OP_ES, 0.7, 2), (slim.OP_ES, 1.0, 3)])
+
+
+@pytest.mark.parametrize("knobs", [{"tri_tile": 256}, {"tri_tile": 512, "tri_chunk": 64},
+                                   {"tri_tile": 1024, "tri_blocks_per_cu": 1},
+                                   {"tri_tile": 256, "tri_blocks_per_cu": 4, "tri_chunk": 32}])
+def test_batch_knobs_and_direct_launch(slim, knobs):
+    graphs = gg.batch_mix(24, 3, 1000, 8000)
+    jobs = [(slim.OP_TR, (0.2, 0.5, 0.8)[i % 3], gg.mix_seed(99, i)) for i in range(len(graphs))]
+    check_batch(slim, graphs, jobs, knobs=knobs, oracle_idx=[0, 1, 5])
+    check_batch(slim, graphs, jobs, knobs=knobs, use_graph=False, runs=1, oracle_idx=[])
+
+
+def test_batch_mix_population_against_oracle(slim):
+    """64 graphs of the mixed population (half G(n,q), half R-MAT, n
+    log-uniform in [1e3, 2e4], average degree 4..64), p = 0.5, per-graph
+    seeds: every graph against the single-graph call and the oracle."""
+    graphs = gg.batch_mix(64, 1, 1000, 20000)
+    jobs = [(slim.OP_TR, 0.5, gg.mix_seed(7, i)) for i in range(len(graphs))]
+    check_batch(slim, graphs, jobs)
+
+
+def test_batch_output_buffers_change(slim):
+    """A replay into other output arrays refreshes the device table."""
+    graphs = [gg.rmat(10, 8, i) for i in range(1, 5)]
+    jobs = [(slim.OP_TR, 0.5, i) for i in range(4)]
+    dgs = [slim.Graph.from_csr(g) for g in graphs]
+    b1 = check_batch(slim, graphs, jobs, dgs=dgs, oracle_idx=[])
+    want = [b1.result_numpy(i) for i in range(4)]
+    import torch
+    b1.row_off_all = torch.full_like(b1.row_off_all, -1)
+    b1.col_all = torch.full_like(b1.col_all, -1)
+    b1.stats_all = torch.zeros_like(b1.stats_all)
+    rp, cp, sp = b1.row_off_all.data_ptr(), b1.col_all.data_ptr(), b1.stats_all.data_ptr()
+    for i in range(4):
+        b1._outs[i].row_off = rp + 8 * int(b1.ro_base[i])
+        b1._outs[i].col = cp + 4 * int(b1.col_base[i])
+        b1._outs[i].stats = sp + 8 * len(slim.STAT_KEYS) * i
+    b1.run()
+    for i in range(4):
+        assert_same(b1.result_numpy(i), want[i])
+
+
+def test_batch_tune_and_cache(slim, tmp_path):
+    graphs = gg.batch_mix(16, 5, 1000, 10000)
+    jobs = [(slim.OP_TR, 0.5, i) for i in range(len(graphs))]
+    dgs = [slim.Graph.from_csr(g) for g in graphs]
+    want = [single(slim, dg, *j) for dg, j in zip(dgs, jobs)]
+    cache = str(tmp_path / "tune.txt")
+    b = slim.Batch(dgs, jobs)
+    b.tune(cache)
+    for i, w in enumerate(want):
+        assert_same(b.result_numpy(i), w)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and "tri_tile=" in lines[0]
+    chosen = {k: b.get(k) for k in ("tri_tile", "tri_blocks_per_cu", "tri_chunk")}
+    b2 = slim.Batch(dgs, jobs)
+    b2.tune(cache)  # a cache hit: same knobs, no new line
+    assert {k: b2.get(k) for k in chosen} == chosen
+    assert len(open(cache).read().splitlines()) == 1
+    for i, w in enumerate(want):
+        assert_same(b2.result_numpy(i), w)
+
+
+def test_batch_errors(slim):
+    import ctypes
+    g = slim.Graph.from_csr(gg.complete(5))
+    with pytest.raises(slim.SlimError) as e:
+        slim.Batch([g], [(7, 0.5, 1)])
+    assert e.value.code == slim.EINVAL
+    with pytest.raises(slim.SlimError) as e:
+        slim.Batch([g], [(slim.OP_TR, float("nan"), 1)])
+    assert e.value.code == slim.EINVAL
+    b = slim.Batch([g], [(slim.OP_TR, 0.5, 1)])
+    rc = slim._lib.slim_batch_run(b._h, b.ws.data_ptr(), b.ws_bytes - 1, b._outs, None)
+    assert rc == slim.ENOMEM
+    outs = (slim.Out * 1)(slim.Out(b._outs[0].row_off, None, None))
+    rc = slim._lib.slim_batch_run(b._h, b.ws.data_ptr(), b.ws_bytes, outs, None)
+    assert rc == slim.EINVAL
+    with pytest.raises(slim.SlimError):
+        b.set("tri_tile", 384)
+    with pytest.raises(slim.SlimError):
+        b.set("use_graph", 2)
+    assert ctypes is not None and os is not None and np is not None

@@ -124,7 +124,8 @@ def test_rmat_medium(slim, scale):
 
 @pytest.mark.parametrize("knobs", [{"tri_chunk": 32}, {"tri_chunk": 64, "tri_blocks_per_cu": 1},
                                    {"tri_chunk": 512, "tri_blocks_per_cu": 3},
-                                   {"tri_blocks_per_cu": 64}])
+                                   {"tri_blocks_per_cu": 64}, {"tri_tile": 256},
+                                   {"tri_tile": 512, "tri_chunk": 64}])
 def test_schedule_independence(slim, knobs):
     """Launch shape and LDS pass size change the schedule, never the result."""
     graphs = [gg.rmat(13, 16, 2), bipartite_plus_matching(3, 300), wheel(5000), gg.complete(70)]
