@@ -208,6 +208,98 @@ SLIM_API int slim_batch_tune(slim_batch_t* b, void* d_ws, uint64_t ws_bytes, con
  * of its runs first. */
 SLIM_API void slim_batch_free(slim_batch_t* b);
 
+/* ------------------------------------------------------------ serving
+ * A compression service inside the process: jobs arrive one at a time
+ * (from any thread), are admitted while the server's device memory stays
+ * within an HBM budget, and run in batches formed continuously -- each of
+ * `n_streams` workers takes every admitted job that is waiting when it
+ * becomes free, so jobs arriving while others are on the GPU start as soon
+ * as a worker and memory are free, and the batches of different workers
+ * overlap on the device.  Each job computes exactly what the single-graph
+ * call computes for its (graph, op, p, seed).  The paper's runtime
+ * (section 4.5, listing `lst:general`) runs one graph at a time; the server
+ * is this library's systems extension.
+ *
+ * Memory: a job holds (a) a device copy of its CSR if it was submitted from
+ * host memory, (b) its output CSR, from admission until slim_result_release,
+ * and (c) its share of its batch's workspace while the batch runs.  The sum
+ * over admitted jobs stays within hbm_budget_bytes (up to alignment slack
+ * of a few KiB per batch); device memory comes from a caching arena that
+ * the server owns and frees at slim_serve_destroy.
+ */
+#define SLIM_HOST 0u   /* slim_job_t.where: CSR arrays in host memory */
+#define SLIM_DEVICE 1u /* slim_job_t.where: CSR arrays in device memory */
+
+typedef struct slim_serve_cfg {
+  uint64_t hbm_budget_bytes; /* device memory the server may hold for jobs (> 0) */
+  uint32_t max_slots;        /* admitted, unreleased jobs at most (0 = 65536) */
+  uint32_t n_streams;        /* workers, each with its own stream (0 = 2; <= 16) */
+  uint32_t max_batch;        /* jobs per batch at most (0 = 4096) */
+  uint32_t pad;              /* must be 0 */
+} slim_serve_cfg_t;
+
+typedef struct slim_job {
+  int32_t op;           /* SLIM_OP_TR or SLIM_OP_ES */
+  int32_t pad;          /* must be 0 */
+  double p;             /* as slim_triangle_reduce / slim_edge_sample */
+  uint64_t seed;
+  const int64_t* row_off; /* CSR (the contract of slim_load_csr; not validated here) */
+  const uint32_t* col;
+  uint64_t n, nnz;
+  uint32_t where;       /* SLIM_HOST: copied to the device when the job's batch
+                           starts, so the arrays must stay valid until the job is
+                           done; SLIM_DEVICE: borrowed until slim_result_release */
+  uint32_t pad2;        /* must be 0 */
+} slim_job_t;
+
+typedef struct slim_result {
+  int32_t status;          /* SLIM_OK, or the code the job failed with */
+  int32_t pad;
+  const int64_t* row_off;  /* device int64[n+1], server-owned until release */
+  const uint32_t* col;     /* device uint32[m_out*2], server-owned until release */
+  uint64_t n;
+  slim_stats_t stats;      /* host copy */
+  double queue_ms;         /* submit -> batch start */
+  double latency_ms;       /* submit -> result ready (host clock) */
+} slim_result_t;
+
+typedef struct slim_serve_stats {
+  uint64_t submitted, completed, failed, cancelled, queued, running, batches;
+  double mean_batch_jobs;
+  double p50_ms, p99_ms, mean_ms, max_ms; /* latency of completed jobs */
+  double jobs_per_s;   /* completed / (last completion - first submission) */
+  double edges_per_s;  /* sum of m_in of completed jobs / the same span */
+  uint64_t hbm_in_use, hbm_peak, hbm_budget;
+} slim_serve_stats_t;
+
+typedef struct slim_server slim_server_t; /* opaque, library-owned */
+
+/* Start a server on the current device.  Errors: SLIM_EINVAL, SLIM_EDEVICE. */
+SLIM_API int slim_serve_create(const slim_serve_cfg_t* cfg, slim_server_t** out);
+/*
+ * Queue a job; *ticket identifies it.  A job that could never fit
+ * (its memory alone exceeds the budget) -> SLIM_EBUDGET; bad op/p/sizes ->
+ * SLIM_EINVAL.  Never blocks on the device.
+ */
+SLIM_API int slim_serve_submit(slim_server_t* s, const slim_job_t* job, uint64_t* ticket);
+/* Result of a finished job; SLIM_EAGAIN if it is not finished yet. */
+SLIM_API int slim_serve_poll(slim_server_t* s, uint64_t ticket, slim_result_t* res);
+/* Blocks until the job is finished, then as slim_serve_poll. */
+SLIM_API int slim_serve_wait(slim_server_t* s, uint64_t ticket, slim_result_t* res);
+/* Drops a job that has not started (SLIM_OK); SLIM_EAGAIN once it runs. */
+SLIM_API int slim_serve_cancel(slim_server_t* s, uint64_t ticket);
+/* Copies a finished job's output CSR into caller memory (host or device;
+ * row_off: n+1 entries, col: 2*m_out entries).  Synchronous. */
+SLIM_API int slim_serve_copy(slim_server_t* s, uint64_t ticket, int64_t* row_off, uint32_t* col);
+/* Returns a finished job's memory to the server and forgets the ticket. */
+SLIM_API int slim_result_release(slim_server_t* s, uint64_t ticket);
+/* Counters and latency percentiles since creation or the last reset. */
+SLIM_API int slim_serve_stats(slim_server_t* s, slim_serve_stats_t* out);
+SLIM_API int slim_serve_reset_stats(slim_server_t* s);
+/* Stops the workers (running batches finish; queued jobs are dropped) and
+ * frees the server's device memory.  NULL is ignored. */
+SLIM_API void slim_serve_destroy(slim_server_t* s);
+
 /* ------------------------------------------------- scheduling knobs
  * Process-wide settings that change launch shapes and the split of work
  * only: results are bit-identical under every setting (the test suite runs

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <mutex>
+#include <vector>
 
 #include "slim_internal.h"
 
@@ -58,5 +59,21 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
              const int64_t* row_off, const uint32_t* col, hipStream_t s, bool profile);
 void prof_reset();
 std::mutex& tuning_mutex();
+
+// A set of graphs as planned on the host: per-graph descriptors with union
+// bases, tile and gather-chunk prefixes, and the set's shape.
+struct SetPlan {
+  SetShape shape;
+  std::vector<GDesc> gd;  // count (+1 slot for the union, filled per run)
+  std::vector<uint64_t> t0c, vt0, et0, ne;
+};
+// Fills bases, prefixes and shape from descriptors whose vb/eb are unset
+// (nv, ne, op, thr, key, inputs given).  Returns SLIM_EINVAL if the union
+// exceeds the id limits.
+int plan_set(const std::vector<GDesc>& graphs, SetPlan& P);
+// Host image of the set header for workspace `ws` (per-graph outputs come
+// from P.gd).
+void fill_header(const SetPlan& P, const SetLayout& L, const Tuning& knobs, void* ws,
+                 std::vector<char>& hdr);
 
 }  // namespace slim

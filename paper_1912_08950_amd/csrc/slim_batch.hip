@@ -14,14 +14,86 @@
 
 using namespace slim;
 
+namespace slim {
+
+int plan_set(const std::vector<GDesc>& graphs, SetPlan& P) {
+  const uint32_t count = (uint32_t)graphs.size();
+  P.gd.assign(count + 1, GDesc{});
+  P.t0c.assign(count + 1, 0);
+  P.vt0.assign(count + 1, 0);
+  P.et0.assign(count + 1, 0);
+  P.ne.assign(count, 0);
+  SetShape& S = P.shape;
+  S = SetShape{};
+  S.count = count;
+  S.gathered = true;
+  uint64_t N = 0, NNZ = 0, maxdeg = 0;
+  for (uint32_t g = 0; g < count; ++g) {
+    GDesc d = graphs[g];
+    d.vb = N;
+    d.eb = NNZ;
+    d.cap = d.ne;
+    P.gd[g] = d;
+    P.ne[g] = d.ne;
+    P.t0c[g] = S.n_c;
+    P.vt0[g] = S.nvt;
+    P.et0[g] = S.net;
+    S.n_c += tiles_of(d.ne, kTile);
+    for (int i = 0; i < 3; ++i) S.n_tri[i] += tiles_of(d.ne, kTriTileMin << i);
+    S.nvt += (d.nv + kTile - 1) / kTile;
+    S.net += (d.ne + kTile - 1) / kTile;
+    if (d.op == SLIM_OP_TR) S.has_tr = true;
+    uint64_t md = d.nv > 0 ? d.nv - 1 : 0;
+    if (d.ne < md) md = d.ne;
+    if (md > maxdeg) maxdeg = md;
+    N += d.nv;
+    NNZ += d.ne;
+  }
+  P.t0c[count] = S.n_c;
+  P.vt0[count] = S.nvt;
+  P.et0[count] = S.net;
+  if (N > 0xffffffffull || NNZ / 2 > 0xffffffffull)
+    return fail(SLIM_EINVAL, "set union too large: n = %llu, m = %llu (limit 2^32-1 each)",
+                (unsigned long long)N, (unsigned long long)(NNZ / 2));
+  S.N = N;
+  S.NNZ = NNZ;
+  S.n_u = tiles_of(NNZ, kTile);
+  S.passes = radix_passes(maxdeg);
+  return SLIM_OK;
+}
+
+void fill_header(const SetPlan& P, const SetLayout& L, const Tuning& knobs, void* ws,
+                 std::vector<char>& hdr) {
+  const uint32_t cnt = P.shape.count;
+  hdr.assign(L.hdr_bytes, 0);
+  char* h = hdr.data();
+  GDesc* gd = reinterpret_cast<GDesc*>(h + L.gd);
+  for (uint32_t g = 0; g < cnt; ++g) gd[g] = P.gd[g];
+  gd[cnt] = union_desc(P.shape, L, ws);
+  uint64_t* t0c = reinterpret_cast<uint64_t*>(h + L.t0c);
+  uint64_t* t0t = reinterpret_cast<uint64_t*>(h + L.t0t);
+  uint64_t* t0u = reinterpret_cast<uint64_t*>(h + L.t0u);
+  uint64_t* vt0 = reinterpret_cast<uint64_t*>(h + L.vt0);
+  uint64_t* et0 = reinterpret_cast<uint64_t*>(h + L.et0);
+  uint64_t acc = 0;
+  for (uint32_t g = 0; g <= cnt; ++g) {
+    t0c[g] = P.t0c[g];
+    vt0[g] = P.vt0[g];
+    et0[g] = P.et0[g];
+    t0t[g] = acc;
+    if (g < cnt) acc += tiles_of(P.ne[g], (uint64_t)knobs.tri_tile);
+  }
+  t0u[0] = 0;
+  t0u[1] = P.shape.n_u;
+}
+
+}  // namespace slim
+
 struct slim_batch {
   int device = 0;
   int num_cu = 0;
   uint32_t count = 0;
-  std::vector<GDesc> gd;  // count + 1; the last is the union (filled per run)
-  std::vector<uint64_t> t0c, vt0, et0;
-  std::vector<uint64_t> ne;  // per graph, for the triangle tile prefixes
-  SetShape shape;
+  SetPlan plan;
   SetLayout layout{};
   Tuning knobs;
   bool use_graph = true;
@@ -56,33 +128,12 @@ void drop_graph(slim_batch* b) {
 
 // Fills the host copy of the set header for workspace `ws` and outputs.
 void build_header(slim_batch* b, void* ws, const slim_out_t* outs) {
-  const SetLayout& L = b->layout;
-  const uint32_t cnt = b->count;
-  b->hdr.assign(L.hdr_bytes, 0);
-  char* h = b->hdr.data();
-  GDesc* gd = reinterpret_cast<GDesc*>(h + L.gd);
-  for (uint32_t g = 0; g < cnt; ++g) {
-    gd[g] = b->gd[g];
-    gd[g].out_row = outs[g].row_off;
-    gd[g].out_col = outs[g].col;
-    gd[g].stats = outs[g].stats;
+  for (uint32_t g = 0; g < b->count; ++g) {
+    b->plan.gd[g].out_row = outs[g].row_off;
+    b->plan.gd[g].out_col = outs[g].col;
+    b->plan.gd[g].stats = outs[g].stats;
   }
-  gd[cnt] = union_desc(b->shape, L, ws);
-  uint64_t* t0c = reinterpret_cast<uint64_t*>(h + L.t0c);
-  uint64_t* t0t = reinterpret_cast<uint64_t*>(h + L.t0t);
-  uint64_t* t0u = reinterpret_cast<uint64_t*>(h + L.t0u);
-  uint64_t* vt0 = reinterpret_cast<uint64_t*>(h + L.vt0);
-  uint64_t* et0 = reinterpret_cast<uint64_t*>(h + L.et0);
-  uint64_t acc = 0;
-  for (uint32_t g = 0; g <= cnt; ++g) {
-    t0c[g] = b->t0c[g];
-    vt0[g] = b->vt0[g];
-    et0[g] = b->et0[g];
-    t0t[g] = acc;
-    if (g < cnt) acc += tiles_of(b->ne[g], (uint64_t)b->knobs.tri_tile);
-  }
-  t0u[0] = 0;
-  t0u[1] = b->shape.n_u;
+  fill_header(b->plan, b->layout, b->knobs, ws, b->hdr);
 }
 
 int check_run(const slim_batch* b, void* ws, uint64_t ws_bytes, const slim_out_t* outs) {
@@ -95,7 +146,7 @@ int check_run(const slim_batch* b, void* ws, uint64_t ws_bytes, const slim_out_t
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(SLIM_EINVAL, "d_ws must be 256-byte aligned");
   for (uint32_t g = 0; g < b->count; ++g) {
     if (!outs[g].row_off) return fail(SLIM_EINVAL, "outs[%u].row_off is NULL", g);
-    if (b->gd[g].ne && !outs[g].col) return fail(SLIM_EINVAL, "outs[%u].col is NULL", g);
+    if (b->plan.gd[g].ne && !outs[g].col) return fail(SLIM_EINVAL, "outs[%u].col is NULL", g);
   }
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
@@ -121,14 +172,14 @@ int run(slim_batch* b, void* ws, uint64_t ws_bytes, const slim_out_t* outs, hipS
     b->last_ws = ws;
   }
   if (!b->use_graph) {
-    run_set(b->shape, b->layout, b->knobs, b->num_cu, ws, nullptr, nullptr, s, false);
+    run_set(b->plan.shape, b->layout, b->knobs, b->num_cu, ws, nullptr, nullptr, s, false);
     return hip_check("slim_batch_run");
   }
   if (!b->exec || b->cap_ws != ws || !same_knobs(b->cap_knobs, b->knobs)) {
     drop_graph(b);
     if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
       return fail(SLIM_EDEVICE, "hipStreamBeginCapture failed");
-    run_set(b->shape, b->layout, b->knobs, b->num_cu, ws, nullptr, nullptr, b->cap_stream, false);
+    run_set(b->plan.shape, b->layout, b->knobs, b->num_cu, ws, nullptr, nullptr, b->cap_stream, false);
     hipGraph_t gr = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap_stream, &gr);
     if (e != hipSuccess || !gr) {
@@ -153,8 +204,8 @@ std::string tune_key(const slim_batch* b) {
   hipDeviceProp_t prop{};
   (void)hipGetDeviceProperties(&prop, b->device);
   std::ostringstream k;
-  k << prop.gcnArchName << ":" << b->num_cu << ":" << b->count << ":" << b->shape.N << ":"
-    << b->shape.NNZ << ":" << (b->shape.has_tr ? "tr" : "es");
+  k << prop.gcnArchName << ":" << b->num_cu << ":" << b->count << ":" << b->plan.shape.N << ":"
+    << b->plan.shape.NNZ << ":" << (b->plan.shape.has_tr ? "tr" : "es");
   std::string s = k.str();
   for (char& c : s)
     if (c == ' ' || c == '\t' || c == '\n') c = '_';
@@ -202,79 +253,38 @@ int slim_batch_create(const slim_graph_t* const* graphs, const slim_job_params_t
   if (count == 0) return fail(SLIM_EINVAL, "a batch needs at least one graph");
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(SLIM_EDEVICE, "hipGetDevice failed");
-  slim_batch* b = new (std::nothrow) slim_batch;
-  if (!b) return fail(SLIM_ENOMEM, "out of host memory");
-  b->device = dev;
-  b->count = count;
-  b->gd.resize(count + 1);
-  b->t0c.resize(count + 1);
-  b->vt0.resize(count + 1);
-  b->et0.resize(count + 1);
-  b->ne.resize(count);
-  SetShape& S = b->shape;
-  S.count = count;
-  S.gathered = true;
-  uint64_t N = 0, NNZ = 0, maxdeg = 0;
+  std::vector<GDesc> gs(count);
+  int num_cu = 0;
   for (uint32_t g = 0; g < count; ++g) {
     const slim_graph* G = graphs[g];
     const slim_job_params_t& J = jobs[g];
-    if (!G) {
-      delete b;
-      return fail(SLIM_EINVAL, "graphs[%u] is NULL", g);
-    }
-    if (G->device != dev) {
-      delete b;
+    if (!G) return fail(SLIM_EINVAL, "graphs[%u] is NULL", g);
+    if (G->device != dev)
       return fail(SLIM_EINVAL, "graphs[%u] lives on device %d, not %d", g, G->device, dev);
-    }
-    if ((J.op != SLIM_OP_TR && J.op != SLIM_OP_ES) || J.pad != 0) {
-      delete b;
+    if ((J.op != SLIM_OP_TR && J.op != SLIM_OP_ES) || J.pad != 0)
       return fail(SLIM_EINVAL, "jobs[%u]: bad op %d", g, J.op);
-    }
-    if (check_p(J.p)) {
-      delete b;
-      return SLIM_EINVAL;
-    }
-    b->num_cu = G->num_cu;
-    GDesc& d = b->gd[g];
-    d = GDesc{};
-    d.vb = N;
+    if (check_p(J.p)) return SLIM_EINVAL;
+    num_cu = G->num_cu;
+    GDesc& d = gs[g];
     d.nv = G->n;
-    d.eb = NNZ;
     d.ne = G->nnz;
     d.thr = threshold(J.p);
     d.k0 = (uint32_t)J.seed;
     d.k1 = (uint32_t)(J.seed >> 32);
     d.op = (uint32_t)J.op;
-    d.cap = G->nnz;
     d.in_row = G->row_off;
     d.in_col = G->col;
-    b->ne[g] = G->nnz;
-    b->t0c[g] = S.n_c;
-    b->vt0[g] = S.nvt;
-    b->et0[g] = S.net;
-    S.n_c += tiles_of(G->nnz, kTile);
-    for (int i = 0; i < 3; ++i) S.n_tri[i] += tiles_of(G->nnz, kTriTileMin << i);
-    S.nvt += (G->n + kTile - 1) / kTile;
-    S.net += (G->nnz + kTile - 1) / kTile;
-    if (J.op == SLIM_OP_TR) S.has_tr = true;
-    uint64_t md = G->n > 0 ? G->n - 1 : 0;
-    if (G->nnz < md) md = G->nnz;
-    if (md > maxdeg) maxdeg = md;
-    N += G->n;
-    NNZ += G->nnz;
   }
-  b->t0c[count] = S.n_c;
-  b->vt0[count] = S.nvt;
-  b->et0[count] = S.net;
-  if (N > 0xffffffffull || NNZ / 2 > 0xffffffffull) {
+  slim_batch* b = new (std::nothrow) slim_batch;
+  if (!b) return fail(SLIM_ENOMEM, "out of host memory");
+  b->device = dev;
+  b->num_cu = num_cu;
+  b->count = count;
+  if (int rc = plan_set(gs, b->plan)) {
     delete b;
-    return fail(SLIM_EINVAL, "batch union too large: n = %llu, m = %llu (limit 2^32-1 each)",
-                (unsigned long long)N, (unsigned long long)(NNZ / 2));
+    return rc;
   }
-  S.N = N;
-  S.NNZ = NNZ;
-  S.n_u = tiles_of(NNZ, kTile);
-  S.passes = radix_passes(maxdeg);
+  const SetShape& S = b->plan.shape;
   b->layout = set_layout(S);
   {
     std::lock_guard<std::mutex> lk(tuning_mutex());
@@ -357,7 +367,7 @@ int slim_batch_tune(slim_batch_t* b, void* d_ws, uint64_t ws_bytes, const slim_o
   Tuning best = b->knobs;
   float best_ms = 0.f;
   int rc = SLIM_OK;
-  if (b->shape.has_tr && b->shape.NNZ > 0) {
+  if (b->plan.shape.has_tr && b->plan.shape.NNZ > 0) {
     rc = time_cfg(best, &best_ms);
     const int tiles[] = {1024, 512, 256};
     const int bpcs[] = {1, 2, 3, 4};

@@ -28,6 +28,9 @@ SYMBOLS = ("slim_last_error", "slim_strerror", "slim_version", "slim_load_csr",
            "slim_graph_free", "slim_workspace_size", "slim_triangle_reduce", "slim_edge_sample",
            "slim_batch_create", "slim_batch_workspace_size", "slim_batch_run", "slim_batch_set",
            "slim_batch_get", "slim_batch_tune", "slim_batch_free",
+           "slim_serve_create", "slim_serve_submit", "slim_serve_poll", "slim_serve_wait",
+           "slim_serve_cancel", "slim_serve_copy", "slim_result_release", "slim_serve_stats",
+           "slim_serve_reset_stats", "slim_serve_destroy",
            "slim_tune_set", "slim_tune_get", "slim_profile_enable", "slim_profile_read")
 
 
@@ -43,6 +46,43 @@ class JobParams(ctypes.Structure):
 class Out(ctypes.Structure):
     _fields_ = [("row_off", ctypes.c_void_p), ("col", ctypes.c_void_p),
                 ("stats", ctypes.c_void_p)]
+
+
+class ServeCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
+                ("n_streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("pad", ctypes.c_int32), ("p", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("row_off", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("n", ctypes.c_uint64), ("nnz", ctypes.c_uint64), ("where", ctypes.c_uint32),
+                ("pad2", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in STAT_KEYS]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("pad", ctypes.c_int32), ("row_off", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("n", ctypes.c_uint64), ("stats", Stats),
+                ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
+SERVE_STAT_KEYS = ("submitted", "completed", "failed", "cancelled", "queued", "running", "batches",
+                   "mean_batch_jobs", "p50_ms", "p99_ms", "mean_ms", "max_ms", "jobs_per_s",
+                   "edges_per_s", "hbm_in_use", "hbm_peak", "hbm_budget")
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = ([(k, ctypes.c_uint64) for k in SERVE_STAT_KEYS[:7]]
+                + [(k, ctypes.c_double) for k in SERVE_STAT_KEYS[7:14]]
+                + [(k, ctypes.c_uint64) for k in SERVE_STAT_KEYS[14:]])
+
+
+HOST, DEVICE = 0, 1
 
 
 class SlimError(RuntimeError):
@@ -87,6 +127,25 @@ def _bind(path: str = LIB_PATH):
     lib.slim_batch_tune.argtypes = [vp, vp, u64, ctypes.POINTER(Out), ctypes.c_char_p, vp]
     lib.slim_batch_free.restype = None
     lib.slim_batch_free.argtypes = [vp]
+    lib.slim_serve_create.restype = i32
+    lib.slim_serve_create.argtypes = [ctypes.POINTER(ServeCfg), ctypes.POINTER(vp)]
+    lib.slim_serve_submit.restype = i32
+    lib.slim_serve_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.POINTER(u64)]
+    for fn in (lib.slim_serve_poll, lib.slim_serve_wait):
+        fn.restype = i32
+        fn.argtypes = [vp, u64, ctypes.POINTER(Result)]
+    lib.slim_serve_cancel.restype = i32
+    lib.slim_serve_cancel.argtypes = [vp, u64]
+    lib.slim_serve_copy.restype = i32
+    lib.slim_serve_copy.argtypes = [vp, u64, vp, vp]
+    lib.slim_result_release.restype = i32
+    lib.slim_result_release.argtypes = [vp, u64]
+    lib.slim_serve_stats.restype = i32
+    lib.slim_serve_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
+    lib.slim_serve_reset_stats.restype = i32
+    lib.slim_serve_reset_stats.argtypes = [vp]
+    lib.slim_serve_destroy.restype = None
+    lib.slim_serve_destroy.argtypes = [vp]
     lib.slim_tune_set.restype = i32
     lib.slim_tune_set.argtypes = [ctypes.c_char_p, ctypes.c_int64]
     lib.slim_tune_get.restype = i32
@@ -326,6 +385,97 @@ class Batch:
             torch.cuda.synchronize(self.device)
             _lib.slim_batch_free(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """In-process compression service (slim_serve_*): HBM-budget admission
+    and continuously formed batches on ``n_streams`` worker streams."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 0, n_streams: int = 2,
+                 max_batch: int = 0, device="cuda:0"):
+        self.device = torch.device(device)
+        cfg = ServeCfg(int(hbm_budget_bytes), int(max_slots), int(n_streams), int(max_batch), 0)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.slim_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}  # ticket -> arrays the job borrows
+
+    def submit(self, graph, op: int, p: float, seed: int) -> int:
+        """Queue a job on a host CSR (graphgen.CSR / numpy arrays, copied to the
+        device by the server) or a device-resident Graph (borrowed)."""
+        if isinstance(graph, Graph):
+            ro, col, n, nnz, where = (graph.row_off.data_ptr(),
+                                      graph.col.data_ptr() if graph.nnz else None,
+                                      graph.n, graph.nnz, DEVICE)
+            keep = graph
+        else:
+            ro_np = np.ascontiguousarray(graph.row_off, dtype=np.int64)
+            col_np = np.ascontiguousarray(graph.col, dtype=np.uint32)
+            ro, col = ro_np.ctypes.data, (col_np.ctypes.data if col_np.size else None)
+            n, nnz, where = ro_np.size - 1, col_np.size, HOST
+            keep = (ro_np, col_np)
+        job = Job(int(op), 0, float(p), int(seed) & (2**64 - 1), ro, col, n, nnz, where, 0)
+        t = ctypes.c_uint64(0)
+        _check(_lib.slim_serve_submit(self._h, ctypes.byref(job), ctypes.byref(t)))
+        self._keep[int(t.value)] = keep
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        r = Result()
+        rc = _lib.slim_serve_poll(self._h, ticket, ctypes.byref(r))
+        if rc == EAGAIN:
+            return None
+        _check(rc)
+        return r
+
+    def wait(self, ticket: int) -> Result:
+        r = Result()
+        _check(_lib.slim_serve_wait(self._h, ticket, ctypes.byref(r)))
+        return r
+
+    def cancel(self, ticket: int) -> bool:
+        rc = _lib.slim_serve_cancel(self._h, ticket)
+        if rc == EAGAIN:
+            return False
+        _check(rc)
+        self._keep.pop(ticket, None)
+        return True
+
+    def result_numpy(self, ticket: int):
+        """Wait for a job and copy its output: (row_off, col, stats dict)."""
+        r = self.wait(ticket)
+        if r.status != OK:
+            raise SlimError(r.status, f"job {ticket} failed")
+        st = {k: int(getattr(r.stats, k)) for k in STAT_KEYS}
+        ro = np.empty(r.n + 1, dtype=np.int64)
+        col = np.empty(max(2 * st["m_out"], 1), dtype=np.uint32)
+        _check(_lib.slim_serve_copy(self._h, ticket, ro.ctypes.data, col.ctypes.data))
+        return ro, col[:2 * st["m_out"]], st
+
+    def release(self, ticket: int):
+        _check(_lib.slim_result_release(self._h, ticket))
+        self._keep.pop(ticket, None)
+
+    def stats(self) -> dict:
+        o = ServeStats()
+        _check(_lib.slim_serve_stats(self._h, ctypes.byref(o)))
+        return {k: getattr(o, k) for k in SERVE_STAT_KEYS}
+
+    def reset_stats(self):
+        _check(_lib.slim_serve_reset_stats(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.slim_serve_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -56,3 +56,23 @@ def test_tuning_knobs():
         slim.tune_set("tri_chunk", 5000)
     with pytest.raises(slim.SlimError):
         slim.tune_set("no_such_knob", 1)
+
+
+def test_batch_and_serve_errors_without_gpu():
+    from paper_1912_08950_amd import slim
+    L = slim._lib
+    h = ctypes.c_void_p()
+    assert L.slim_batch_create(None, None, 0, ctypes.byref(h)) == slim.EINVAL
+    b = ctypes.c_uint64()
+    assert L.slim_batch_workspace_size(None, ctypes.byref(b)) == slim.EINVAL
+    assert L.slim_batch_run(None, None, 0, None, None) == slim.EINVAL
+    L.slim_batch_free(None)
+    assert L.slim_serve_create(None, ctypes.byref(h)) == slim.EINVAL
+    cfg = slim.ServeCfg(0, 0, 0, 0, 0)
+    assert L.slim_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == slim.EINVAL
+    cfg = slim.ServeCfg(1 << 30, 0, 17, 0, 0)
+    assert L.slim_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == slim.EINVAL
+    t = ctypes.c_uint64()
+    assert L.slim_serve_submit(None, None, ctypes.byref(t)) == slim.EINVAL
+    assert L.slim_result_release(None, 1) == slim.EINVAL
+    L.slim_serve_destroy(None)
