@@ -8,7 +8,16 @@ synthetic R-MAT (a,b,c,d = .57,.19,.19,.05, edge factor 16, ids permuted,
 symmetrized, loops and duplicates removed) standing in for the paper's real
 graphs.  Prints one JSON line on stdout; progress goes to stderr.
 
+Beside it, on the same GPU: a batch of 4096 graphs (half G(n,q), half
+R-MAT, n log-uniform in [1e3, 2e5], average degree uniform in [4, 64],
+p = 0.5, per-graph seeds) run as one captured launch sequence against 4096
+plain per-graph calls, with every output compared; and a serving sweep --
+Poisson arrivals of jobs drawn from that population plus 1% R-MAT scale-22
+jobs, p uniform in {0.2, 0.5, 0.8}, CSRs resident in HBM, a 200 GB budget --
+reporting throughput and p50/p99 latency per arrival rate.
+
   python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--scale 24] [--p 0.5]
+                  [--batch-count 4096] [--serve-rates 100,...,5000] [--serve-seconds 2]
 """
 import argparse
 import json
@@ -119,6 +128,163 @@ def cpu_baseline(scale):
             "seconds": round(dt, 2)}
 
 
+def bench_batch(args, log):
+    """Batched vs plain Triangle p-1-Reduction on the mixed population."""
+    import numpy as np
+    import torch
+
+    from paper_1912_08950_amd import graphgen, slim
+
+    t0 = time.perf_counter()
+    gs = graphgen.batch_mix(args.batch_count, args.batch_seed)
+    m_total = sum(g.m for g in gs)
+    log(f"batch population: {len(gs)} graphs, m = {m_total} in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    dgs = [slim.Graph.from_csr(g, device=dev) for g in gs]
+    jobs = [(slim.OP_TR, args.p, graphgen.mix_seed(args.batch_seed, i)) for i in range(len(gs))]
+    b = slim.Batch(dgs, jobs)
+    log(f"batch workspace {b.ws_bytes / 2**30:.1f} GiB; tuning")
+    t0 = time.perf_counter()
+    b.tune()
+    knobs = {k: b.get(k) for k in ("tri_tile", "tri_blocks_per_cu", "tri_chunk")}
+    log(f"tuned in {time.perf_counter() - t0:.1f}s: {knobs}")
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.run()
+    torch.cuda.synchronize()
+    reps = max(args.steps, 3)
+    e0.record(stream)
+    for _ in range(reps):
+        b.run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batched_ms = e0.elapsed_time(e1) / reps
+    log(f"batched: {batched_ms:.2f} ms per run of {len(gs)} graphs")
+    # plain: one call per graph into flat outputs laid out like the batch's
+    ws_bytes = max(dg.workspace_size(slim.OP_TR) for dg in dgs)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    ro_all = torch.empty_like(b.row_off_all)
+    col_all = torch.empty_like(b.col_all)
+    st_all = torch.zeros_like(b.stats_all)
+    L = slim._lib
+    handle = stream.cuda_stream
+
+    def plain():
+        for i, (dg, (op, p, seed)) in enumerate(zip(dgs, jobs)):
+            rc = L.slim_triangle_reduce(dg._h, p, seed, ws.data_ptr(), ws_bytes,
+                                        ro_all.data_ptr() + 8 * int(b.ro_base[i]),
+                                        col_all.data_ptr() + 4 * int(b.col_base[i]),
+                                        st_all.data_ptr() + 8 * len(slim.STAT_KEYS) * i, handle)
+            if rc != 0:
+                raise slim.SlimError(rc, L.slim_last_error().decode())
+
+    plain()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        plain()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / reps
+    log(f"plain: {plain_ms:.2f} ms for {len(gs)} calls")
+    identical = bool(torch.equal(ro_all, b.row_off_all) and torch.equal(st_all, b.stats_all))
+    ro_np = b.row_off_all.cpu().numpy()  # compare the used part of each graph's columns
+    for i in range(len(gs)):
+        c0, k = int(b.col_base[i]), int(ro_np[int(b.ro_base[i + 1]) - 1])
+        if k and not torch.equal(col_all[c0:c0 + k], b.col_all[c0:c0 + k]):
+            identical = False
+            break
+    stats = b.stats_all.cpu().numpy()
+    b.close()
+    del b, dgs, ws, ro_all, col_all, st_all
+    torch.cuda.empty_cache()
+    return {"workload": f"{len(gs)} graphs, half G(n,q) half R-MAT, n log-uniform [1e3, 2e5], "
+                        f"avg degree uniform [4, 64], p={args.p}, per-graph seeds",
+            "graphs": len(gs), "m_total": int(m_total), "triangles": int(stats[:, 2].sum()),
+            "batched_ms": batched_ms, "plain_ms": plain_ms, "speedup": plain_ms / batched_ms,
+            "batched_edges_per_s": m_total / (batched_ms * 1e-3),
+            "plain_edges_per_s": m_total / (plain_ms * 1e-3),
+            "knobs": knobs, "identical_to_plain": identical}
+
+
+def bench_serve(args, log):
+    """Poisson serving sweep with resident CSRs."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_1912_08950_amd import graphgen, slim
+
+    dev = torch.device("cuda:0")
+    pool = graphgen.batch_mix(args.serve_pool, args.batch_seed + 1)
+    big = graphgen.rmat(22, 16, 3)
+    dpool = [slim.Graph.from_csr(g, device=dev) for g in pool]
+    dbig = slim.Graph.from_csr(big, device=dev)
+    log(f"serve pool: {len(pool)} graphs + R-MAT s22 (m = {big.m})")
+    srv = slim.Server(200 << 30, n_streams=args.serve_streams)
+    out = []
+    for rate in [float(x) for x in args.serve_rates.split(",") if x]:
+        rng = np.random.default_rng(int(rate))
+        njobs = max(20, int(rate * args.serve_seconds))
+        gaps = rng.exponential(1.0 / rate, njobs)
+        pick_big = rng.random(njobs) < 0.01
+        pick = rng.integers(0, len(dpool), njobs)
+        ps = rng.choice([0.2, 0.5, 0.8], njobs)
+        tickets = []
+        cv = threading.Condition()
+        done = [False]
+
+        def reaper():
+            k = 0
+            while True:
+                with cv:
+                    while k >= len(tickets) and not done[0]:
+                        cv.wait()
+                    if k >= len(tickets) and done[0]:
+                        return
+                    t = tickets[k]
+                srv.wait(t)
+                srv.release(t)
+                k += 1
+
+        srv.reset_stats()
+        th = threading.Thread(target=reaper)
+        th.start()
+        t_next = time.perf_counter()
+        m_offered = 0
+        for k in range(njobs):
+            t_next += gaps[k]
+            while time.perf_counter() < t_next:
+                pass
+            g = dbig if pick_big[k] else dpool[pick[k]]
+            m_offered += g.m
+            t = srv.submit(g, slim.OP_TR, float(ps[k]), graphgen.mix_seed(int(rate), k))
+            with cv:
+                tickets.append(t)
+                cv.notify()
+        with cv:
+            done[0] = True
+            cv.notify()
+        th.join()
+        st = srv.stats()
+        row = {"rate_jobs_per_s": rate, "jobs": njobs, "big_jobs": int(pick_big.sum()),
+               "achieved_jobs_per_s": st["jobs_per_s"], "edges_per_s": st["edges_per_s"],
+               "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+               "max_ms": st["max_ms"], "batches": st["batches"],
+               "mean_batch_jobs": st["mean_batch_jobs"], "hbm_peak_gib": st["hbm_peak"] / 2**30}
+        log(f"serve rate {rate:g}/s: {row}")
+        out.append(row)
+    srv.close()
+    del dpool, dbig
+    torch.cuda.empty_cache()
+    return {"workload": f"Poisson arrivals, jobs from {args.serve_pool} graphs of the batch "
+                        f"population plus 1% R-MAT s22, p in {{0.2,0.5,0.8}}, CSRs resident, "
+                        f"200 GB budget, {args.serve_streams} worker streams, "
+                        f"{args.serve_seconds:g} s of arrivals per rate",
+            "sweep": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +298,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--batch-count", type=int, default=4096, help="0 skips the batch section")
+    ap.add_argument("--batch-seed", type=int, default=1)
+    ap.add_argument("--serve-rates", default="100,200,500,1000,2000,5000",
+                    help="arrival rates (jobs/s); empty skips the serving section")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-pool", type=int, default=256)
+    ap.add_argument("--serve-streams", type=int, default=2)
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -225,6 +398,14 @@ def main():
                      "scan_bytes_per_s": 4 * work["sum_out_pairs"] / (tri_ms * 1e-3)},
         "step_algorithmic_gbs": step_bytes(g, work, stats["m_out"]) / (ms_per_step * 1e-3) / 1e9,
     }
+    del bufs, es_bufs, dg
+    torch.cuda.empty_cache()
+    if args.batch_count > 0:
+        result["batch"] = bench_batch(args, log)
+    if args.serve_rates:
+        result["serve"] = bench_serve(args, log)
+        sw = result["serve"]["sweep"]
+        result["p99_ms"] = {f"{r['rate_jobs_per_s']:g}": r["p99_ms"] for r in sw}
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on R-MAT scale {args.cpu_scale}")
         result["cpu_baseline"] = cpu_baseline(args.cpu_scale)

@@ -171,8 +171,9 @@ int run(slim_batch* b, void* ws, uint64_t ws_bytes, const slim_out_t* outs, hipS
     b->last_hdr = b->hdr;
     b->last_ws = ws;
   }
-  if (!b->use_graph) {
-    run_set(b->plan.shape, b->layout, b->knobs, b->num_cu, ws, nullptr, nullptr, s, false);
+  if (!b->use_graph) {  // direct launches: phases are timed when profiling is on
+    prof_reset();
+    run_set(b->plan.shape, b->layout, b->knobs, b->num_cu, ws, nullptr, nullptr, s, true);
     return hip_check("slim_batch_run");
   }
   if (!b->exec || b->cap_ws != ws || !same_knobs(b->cap_knobs, b->knobs)) {

@@ -68,6 +68,11 @@ def _load():
                                  u64, u64, ctypes.c_void_p, ctypes.c_void_p]
     lib.sg_copy_free.restype = None
     lib.sg_num_threads.restype = ctypes.c_int
+    vp = ctypes.c_void_p
+    lib.sg_gen_many.argtypes = [u64, vp, vp, vp, vp, vp, vp,
+                                ctypes.POINTER(ctypes.POINTER(ctypes.c_int64)),
+                                ctypes.POINTER(ctypes.POINTER(ctypes.c_uint32)), vp]
+    lib.sg_gen_many.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -212,18 +217,53 @@ def batch_mix(count: int, seed: int, n_lo: int = 1000, n_hi: int = 200000, d_lo:
     """`count` graphs, even indices G(n, q) and odd indices R-MAT, with n
     log-uniform in [n_lo, n_hi] and average degree uniform in [d_lo, d_hi]
     (parameters from numpy's PCG64 seeded with `seed`; graph i's generator
-    seed is mix_seed(seed, i)).  Returns a list of CSR."""
+    seed is mix_seed(seed, i)).  Generated in parallel across graphs; graph
+    i equals what er() / rmat() return for its parameters.  Returns a list
+    of CSR."""
     rng = np.random.default_rng(seed)
-    ns = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count)).astype(np.int64)
+    ns = np.maximum(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count)).astype(np.int64), 2)
+    ds = rng.uniform(d_lo, d_hi, count)
+    kind = np.array([i % 2 for i in range(count)], dtype=np.int32)
+    seeds = np.array([mix_seed(seed, i) & 0x7FFFFFFFFFFFFFFF for i in range(count)], dtype=np.uint64)
+    scales = np.array([max(1, int(np.ceil(np.log2(int(n))))) for n in ns], dtype=np.int32)
+    samples = np.array([int(round(d / 2 * n * ((1 << int(s)) / n) ** 2))
+                        for n, d, s in zip(ns, ds, scales)], dtype=np.uint64)
+    lib = _load()
+    ro_ps = (ctypes.POINTER(ctypes.c_int64) * count)()
+    col_ps = (ctypes.POINTER(ctypes.c_uint32) * count)()
+    nnzs = np.zeros(count, dtype=np.uint64)
+    ns_u = ns.astype(np.uint64)
+    rc = lib.sg_gen_many(count, kind.ctypes.data, ns_u.ctypes.data, ds.ctypes.data,
+                         seeds.ctypes.data, scales.ctypes.data, samples.ctypes.data, ro_ps, col_ps,
+                         nnzs.ctypes.data)
+    out = []
+    for i in range(count):
+        n, nnz = int(ns[i]), int(nnzs[i])
+        name = (f"er_n{n}_d{ds[i]:g}_s{int(seeds[i])}" if kind[i] == 0 else
+                f"rmat_s{int(scales[i])}_n{n}_s{int(seeds[i])}")
+        if not ro_ps[i]:
+            raise RuntimeError(f"graph generator failed (rc={rc}) for {name}")
+        row_off = np.empty(n + 1, dtype=np.int64)
+        col = np.empty(nnz, dtype=np.uint32)
+        lib.sg_copy_free(ro_ps[i], col_ps[i], n, nnz, row_off.ctypes.data, col.ctypes.data)
+        out.append(CSR(row_off, col, name))
+    if rc != 0:
+        raise RuntimeError(f"graph generator failed (rc={rc})")
+    return out
+
+
+def batch_mix_params(count: int, seed: int, n_lo: int = 1000, n_hi: int = 200000,
+                     d_lo: float = 4.0, d_hi: float = 64.0):
+    """The per-graph (kind, n, d, generator seed, scale, samples) that
+    batch_mix(count, seed, ...) draws, for checking it graph by graph."""
+    rng = np.random.default_rng(seed)
+    ns = np.maximum(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count)).astype(np.int64), 2)
     ds = rng.uniform(d_lo, d_hi, count)
     out = []
     for i in range(count):
-        n, d, s = int(max(ns[i], 2)), float(ds[i]), mix_seed(seed, i) & 0x7FFFFFFFFFFFFFFF
-        if i % 2 == 0:
-            g = er(n, d, s)
-        else:
-            scale = max(1, int(np.ceil(np.log2(n))))
-            samples = int(round(d / 2 * n * ((1 << scale) / n) ** 2))
-            g = rmat(scale, d / 2, s, n=n, samples=samples)
-        out.append(g)
+        n, d = int(ns[i]), float(ds[i])
+        s = mix_seed(seed, i) & 0x7FFFFFFFFFFFFFFF
+        scale = max(1, int(np.ceil(np.log2(n))))
+        out.append(("er" if i % 2 == 0 else "rmat", n, d, s, scale,
+                    int(round(d / 2 * n * ((1 << scale) / n) ** 2))))
     return out

@@ -57,7 +57,7 @@ static inline double gg_unit(gg_rng* r) {
 /* ------------------------------------------------- edge list -> CSR */
 
 static void gg_sort_u32(uint32_t* a, int64_t len, uint32_t* tmp) {
-  if (len <= 32) {
+  if (len <= 64) {
     for (int64_t i = 1; i < len; ++i) {
       uint32_t x = a[i];
       int64_t j = i - 1;
@@ -69,10 +69,14 @@ static void gg_sort_u32(uint32_t* a, int64_t len, uint32_t* tmp) {
     }
     return;
   }
-  /* LSD radix sort, 4 passes of 8 bits, ping-pong with tmp */
+  /* LSD radix sort, 8-bit passes over the significant bits, ping-pong with tmp */
+  uint32_t mx = 0;
+  for (int64_t i = 0; i < len; ++i) mx = a[i] > mx ? a[i] : mx;
+  int passes = 1;
+  while (passes < 4 && (mx >> (8 * passes)) != 0) ++passes;
   uint32_t* src = a;
   uint32_t* dst = tmp;
-  for (int shift = 0; shift < 32; shift += 8) {
+  for (int shift = 0; shift < 8 * passes; shift += 8) {
     int64_t cnt[257];
     memset(cnt, 0, sizeof(cnt));
     for (int64_t i = 0; i < len; ++i) cnt[((src[i] >> shift) & 255u) + 1]++;
@@ -82,7 +86,7 @@ static void gg_sort_u32(uint32_t* a, int64_t len, uint32_t* tmp) {
     src = dst;
     dst = t;
   }
-  /* after 4 passes the data is back in a */
+  if (src != a) memcpy(a, src, (size_t)len * sizeof(uint32_t));
 }
 
 /*
@@ -94,12 +98,29 @@ static int gg_pairs_to_csr(uint64_t n, const uint32_t* pu, const uint32_t* pv, u
                            int64_t** row_off_out, uint32_t** col_out, uint64_t* nnz_out) {
   int64_t* cnt = (int64_t*)calloc(n + 1, sizeof(int64_t));
   if (!cnt) return -1;
+  /* inside an enclosing parallel region (sg_gen_many) the loops below run on
+   * one thread, so plain increments suffice */
+  int serial = 0;
+#ifdef _OPENMP
+  serial = omp_in_parallel();
+#else
+  serial = 1;
+#endif
+  if (serial) {
+    for (uint64_t i = 0; i < npairs; ++i) {
+      uint32_t u = pu[i], v = pv[i];
+      if (u == v || u >= n || v >= n) continue;
+      cnt[u]++;
+      cnt[v]++;
+    }
+  } else {
 #pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < (int64_t)npairs; ++i) {
-    uint32_t u = pu[i], v = pv[i];
-    if (u == v || u >= n || v >= n) continue;
-    __atomic_fetch_add(&cnt[u], 1, __ATOMIC_RELAXED);
-    __atomic_fetch_add(&cnt[v], 1, __ATOMIC_RELAXED);
+    for (int64_t i = 0; i < (int64_t)npairs; ++i) {
+      uint32_t u = pu[i], v = pv[i];
+      if (u == v || u >= n || v >= n) continue;
+      __atomic_fetch_add(&cnt[u], 1, __ATOMIC_RELAXED);
+      __atomic_fetch_add(&cnt[v], 1, __ATOMIC_RELAXED);
+    }
   }
   int64_t* off = (int64_t*)malloc((n + 1) * sizeof(int64_t));
   if (!off) {
@@ -117,14 +138,23 @@ static int gg_pairs_to_csr(uint64_t n, const uint32_t* pu, const uint32_t* pv, u
   }
   /* cnt becomes the per-row cursor */
   memcpy(cnt, off, n * sizeof(int64_t));
+  if (serial) {
+    for (uint64_t i = 0; i < npairs; ++i) {
+      uint32_t u = pu[i], v = pv[i];
+      if (u == v || u >= n || v >= n) continue;
+      adj[cnt[u]++] = v;
+      adj[cnt[v]++] = u;
+    }
+  } else {
 #pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < (int64_t)npairs; ++i) {
-    uint32_t u = pu[i], v = pv[i];
-    if (u == v || u >= n || v >= n) continue;
-    int64_t a = __atomic_fetch_add(&cnt[u], 1, __ATOMIC_RELAXED);
-    int64_t b = __atomic_fetch_add(&cnt[v], 1, __ATOMIC_RELAXED);
-    adj[a] = v;
-    adj[b] = u;
+    for (int64_t i = 0; i < (int64_t)npairs; ++i) {
+      uint32_t u = pu[i], v = pv[i];
+      if (u == v || u >= n || v >= n) continue;
+      int64_t a = __atomic_fetch_add(&cnt[u], 1, __ATOMIC_RELAXED);
+      int64_t b = __atomic_fetch_add(&cnt[v], 1, __ATOMIC_RELAXED);
+      adj[a] = v;
+      adj[b] = u;
+    }
   }
   /* sort + dedup every row in place; cnt[r] := deduplicated length */
 #pragma omp parallel
@@ -335,6 +365,60 @@ int sg_gen_rmat(int scale, uint64_t n, uint64_t samples, double a, double b, dou
   int rc = gg_pairs_to_csr(n, pu, pv, samples, row_off, col, nnz);
   free(pu);
   free(pv);
+  return rc;
+}
+
+/* ------------------------------------------------------ many graphs */
+
+/*
+ * Generates `count` graphs at once, one graph per thread (the generators'
+ * own parallel loops then run on one thread each), largest first.  Graph i
+ * is G(n[i], d[i]/(n[i]-1)) with seed[i] if kind[i] == 0, else R-MAT at
+ * scale[i] with n[i] vertices and samples[i] samples.  Output i is exactly
+ * what the single-graph call returns.  Returns 0, or the first failing
+ * graph's code (outputs of other graphs are still filled or NULL).
+ */
+int sg_gen_many(uint64_t count, const int32_t* kind, const uint64_t* n, const double* d,
+                const uint64_t* seed, const int32_t* scale, const uint64_t* samples,
+                int64_t** row_offs, uint32_t** cols, uint64_t* nnzs) {
+  uint64_t* order = (uint64_t*)malloc((size_t)(count > 0 ? count : 1) * sizeof(uint64_t));
+  double* work = (double*)malloc((size_t)(count > 0 ? count : 1) * sizeof(double));
+  if (!order || !work) {
+    free(order);
+    free(work);
+    return -1;
+  }
+  for (uint64_t i = 0; i < count; ++i) {
+    order[i] = i;
+    work[i] = (double)n[i] * (kind[i] == 0 ? d[i] : (double)samples[i] / (double)(n[i] ? n[i] : 1));
+    row_offs[i] = NULL;
+    cols[i] = NULL;
+    nnzs[i] = 0;
+  }
+  /* largest first: insertion into a max-ordered list is fine for a few thousand */
+  for (uint64_t i = 1; i < count; ++i) {
+    uint64_t x = order[i];
+    int64_t j = (int64_t)i - 1;
+    while (j >= 0 && work[order[j]] < work[x]) {
+      order[j + 1] = order[j];
+      --j;
+    }
+    order[j + 1] = x;
+  }
+  int rc = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t k = 0; k < (int64_t)count; ++k) {
+    const uint64_t i = order[k];
+    int r = kind[i] == 0 ? sg_gen_er(n[i], d[i], seed[i], &row_offs[i], &cols[i], &nnzs[i])
+                         : sg_gen_rmat(scale[i], n[i], samples[i], 0.57, 0.19, 0.19, 1, seed[i],
+                                       &row_offs[i], &cols[i], &nnzs[i]);
+    if (r != 0) {
+#pragma omp critical
+      if (rc == 0) rc = r;
+    }
+  }
+  free(order);
+  free(work);
   return rc;
 }
 

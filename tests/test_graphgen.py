@@ -40,3 +40,16 @@ def test_rmat_shape():
 def test_rmat_reject_above_n():
     g = gg.rmat(10, 8, 5, n=700)
     assert g.n == 700 and (g.col < 700).all()
+
+
+def test_batch_mix_equals_single_generators():
+    """The many-graph generator returns exactly the single-graph generators'
+    output for each drawn parameter set, and draws the stated population."""
+    import numpy as np
+    gs = gg.batch_mix(48, 4, 1000, 30000)
+    for g, (kind, n, d, s, scale, samples) in zip(gs, gg.batch_mix_params(48, 4, 1000, 30000)):
+        h = gg.er(n, d, s) if kind == "er" else gg.rmat(scale, d / 2, s, n=n, samples=samples)
+        assert g.n == n and np.array_equal(g.row_off, h.row_off) and np.array_equal(g.col, h.col)
+        assert 1000 <= n <= 30000 and 4 <= d <= 64
+        assert 0.5 * d <= 2 * g.m / g.n <= 1.1 * d, (kind, n, d, 2 * g.m / g.n)
+    assert gg.mix_seed(1, 0) != gg.mix_seed(1, 1) and gg.mix_seed(1, 0) == gg.mix_seed(1, 0)
