@@ -143,7 +143,15 @@ def bench_batch(args, log):
     dgs = [slim.Graph.from_csr(g, device=dev) for g in gs]
     jobs = [(slim.OP_TR, args.p, graphgen.mix_seed(args.batch_seed, i)) for i in range(len(gs))]
     b = slim.Batch(dgs, jobs)
-    log(f"batch workspace {b.ws_bytes / 2**30:.1f} GiB; tuning")
+    log(f"batch workspace {b.ws_bytes / 2**30:.1f} GiB; one direct run")
+    slim.profile_enable(True)
+    b.set("use_graph", 0)
+    b.run()
+    torch.cuda.synchronize()
+    log(f"direct run phases {slim.profile_read()}")
+    b.set("use_graph", 1)
+    b.set("verbose", 1)
+    log("tuning")
     t0 = time.perf_counter()
     b.tune()
     knobs = {k: b.get(k) for k in ("tri_tile", "tri_blocks_per_cu", "tri_chunk")}

@@ -188,7 +188,8 @@ SLIM_API int slim_batch_run(slim_batch_t* b, void* d_ws, uint64_t ws_bytes, cons
                             void* stream);
 /*
  * Scheduling knobs of one batch (same keys as slim_tune_set, plus
- * "use_graph" 0/1: replay a captured HIP graph, default 1).  Results never
+ * "use_graph" 0/1: replay a captured HIP graph, default 1; "verbose" 0/1:
+ * slim_batch_tune reports each candidate's time on stderr).  Results never
  * depend on them.
  */
 SLIM_API int slim_batch_set(slim_batch_t* b, const char* key, int64_t value);

@@ -97,6 +97,7 @@ struct slim_batch {
   SetLayout layout{};
   Tuning knobs;
   bool use_graph = true;
+  bool verbose = false;  // the tuner reports each candidate on stderr
   // header upload
   std::vector<char> hdr, last_hdr;
   void* pinned = nullptr;
@@ -314,9 +315,9 @@ int slim_batch_run(slim_batch_t* b, void* d_ws, uint64_t ws_bytes, const slim_ou
 
 int slim_batch_set(slim_batch_t* b, const char* key, int64_t value) {
   if (!b || !key) return fail(SLIM_EINVAL, "NULL argument");
-  if (std::strcmp(key, "use_graph") == 0) {
-    if (value != 0 && value != 1) return fail(SLIM_EINVAL, "use_graph must be 0 or 1");
-    b->use_graph = value != 0;
+  if (std::strcmp(key, "use_graph") == 0 || std::strcmp(key, "verbose") == 0) {
+    if (value != 0 && value != 1) return fail(SLIM_EINVAL, "%s must be 0 or 1", key);
+    (key[0] == 'u' ? b->use_graph : b->verbose) = value != 0;
     return ok();
   }
   if (!tune_apply(b->knobs, key, value))
@@ -327,8 +328,8 @@ int slim_batch_set(slim_batch_t* b, const char* key, int64_t value) {
 
 int slim_batch_get(const slim_batch_t* b, const char* key, int64_t* value) {
   if (!b || !key || !value) return fail(SLIM_EINVAL, "NULL argument");
-  if (std::strcmp(key, "use_graph") == 0) {
-    *value = b->use_graph ? 1 : 0;
+  if (std::strcmp(key, "use_graph") == 0 || std::strcmp(key, "verbose") == 0) {
+    *value = (key[0] == 'u' ? b->use_graph : b->verbose) ? 1 : 0;
     return ok();
   }
   if (!tune_read(b->knobs, key, value)) return fail(SLIM_EINVAL, "unknown knob '%s'", key);
@@ -363,6 +364,11 @@ int slim_batch_tune(slim_batch_t* b, void* d_ws, uint64_t ws_bytes, const slim_o
       if (x < best) best = x;
     }
     *ms = best;
+    if (b->verbose) {
+      std::fprintf(stderr, "[slim tune] tri_tile=%d tri_blocks_per_cu=%d tri_chunk=%d: %.3f ms\n",
+                   t.tri_tile, t.tri_blocks_per_cu, t.tri_chunk, best);
+      std::fflush(stderr);
+    }
     return SLIM_OK;
   };
   Tuning best = b->knobs;

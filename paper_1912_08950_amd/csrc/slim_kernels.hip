@@ -279,7 +279,7 @@ __device__ __forceinline__ uint32_t graph_of_tile(const uint64_t* tile0, uint32_
                                                   uint64_t t) {
   uint32_t lo = 0, hi = count;
   while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
+    const uint32_t mid = lo + ((hi - lo) >> 1);
     if (tile0[mid] <= t)
       lo = mid;
     else
@@ -293,7 +293,7 @@ __device__ __forceinline__ uint32_t first_row_at(const int64_t* row_off, uint64_
                                                  uint64_t ve, int64_t j) {
   uint64_t lo = vb, hi = ve;
   while (lo < hi) {
-    const uint64_t mid = (lo + hi) >> 1;
+    const uint64_t mid = lo + ((hi - lo) >> 1);
     if (row_off[mid] < j)
       lo = mid + 1;
     else
@@ -656,7 +656,7 @@ __global__ __launch_bounds__(kBlock) void k_validate_entries(const int64_t* row_
     if ((int64_t)j > row_off[r] && col[j - 1] >= c) e |= 8u;
     int64_t lo = row_off[c], hi = row_off[c + 1];
     while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
+      const int64_t mid = lo + ((hi - lo) >> 1);
       if (col[mid] < r)
         lo = mid + 1;
       else

@@ -254,7 +254,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     const uint32_t fs = C.a.fstart[r], fe = C.a.fstart[r + 1];
     uint32_t lo = yr.x, hi = yr.y;
     while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
+      const uint32_t mid = lo + ((hi - lo) >> 1);
       if (C.a.dag_col[mid] < x)
         lo = mid + 1;
       else
@@ -299,7 +299,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
   if (ws < we) {  // in-edge holding item ws: last k with ie_pre[k] <= ws
     uint32_t lo = 0, hi = nin;
     while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
+      const uint32_t mid = lo + ((hi - lo) >> 1);
       if (S.ie_pre[mid] <= ws)
         lo = mid;
       else
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
             if (tid == 0) {  // first bw index at or past the end of row r in the tile
               uint32_t lo = cur, hi = nbw;
               while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
+                const uint32_t mid = lo + ((hi - lo) >> 1);
                 if ((uint32_t)S.bw[mid] < eb)
                   lo = mid + 1;
                 else

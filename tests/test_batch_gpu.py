@@ -155,3 +155,41 @@ def test_batch_errors(slim):
     with pytest.raises(slim.SlimError):
         b.set("use_graph", 2)
     assert ctypes is not None and os is not None and np is not None
+
+
+def test_batch_union_beyond_2_31_edges(slim):
+    """One R-MAT s20 graph batched 134 times: the union has m = 2.15e9 > 2^31
+    edges, so DAG positions of the last jobs exceed 2^31 (a midpoint of two
+    such positions overflows 32 bits unless computed as lo + (hi-lo)/2).
+    Every job equals its single-graph call; the seed-1 job equals the
+    oracle's stored digest."""
+    import json
+    import os
+
+    import torch
+    from make_oracle_digests import csr_digest
+
+    g = gg.rmat(20, 16, 1)
+    copies = (2**31) // g.m + 6
+    assert copies * g.m > 2**31
+    dg = slim.Graph.from_csr(g)
+    jobs = [(slim.OP_TR, 0.5, s) for s in range(1, copies + 1)]
+    b = slim.Batch([dg] * copies, jobs)
+    b.run()
+    torch.cuda.synchronize()
+    bufs = slim.Buffers(dg, slim.OP_TR)
+    for i in (0, 1, copies // 2, copies - 3, copies - 2, copies - 1):
+        slim.triangle_reduce(dg, 0.5, jobs[i][2], bufs)
+        torch.cuda.synchronize()
+        a, z = int(b.ro_base[i]), int(b.ro_base[i + 1])
+        assert torch.equal(b.row_off_all[a:z], bufs.out_row_off), i
+        k = int(bufs.out_row_off[-1])
+        c0 = int(b.col_base[i])
+        assert torch.equal(b.col_all[c0:c0 + k], bufs.out_col[:k]), i
+        assert torch.equal(b.stats_all[i], bufs.stats), i
+    d = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                    "oracle_digests.json")))["rmat20_tr_p0.5"]
+    ro, col, st = b.result_numpy(0)
+    assert csr_digest(ro, col) == d["out_sha256"] and st["triangles"] == d["stats"]["T"]
+    ro, col, st = b.result_numpy(copies - 1)
+    assert st["triangles"] == d["stats"]["T"]
