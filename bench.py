@@ -239,41 +239,25 @@ def bench_serve(args, log):
         pick_big = rng.random(njobs) < 0.01
         pick = rng.integers(0, len(dpool), njobs)
         ps = rng.choice([0.2, 0.5, 0.8], njobs)
-        tickets = []
-        cv = threading.Condition()
-        done = [False]
+        srv.reset_stats()
+        # a client thread takes results in completion order and releases them
+        got = [0]
 
         def reaper():
-            k = 0
-            while True:
-                with cv:
-                    while k >= len(tickets) and not done[0]:
-                        cv.wait()
-                    if k >= len(tickets) and done[0]:
-                        return
-                    t = tickets[k]
-                srv.wait(t)
-                srv.release(t)
-                k += 1
+            while got[0] < njobs:
+                tr = srv.next(-1)
+                srv.release(tr[0])
+                got[0] += 1
 
-        srv.reset_stats()
         th = threading.Thread(target=reaper)
         th.start()
         t_next = time.perf_counter()
-        m_offered = 0
         for k in range(njobs):
             t_next += gaps[k]
             while time.perf_counter() < t_next:
                 pass
             g = dbig if pick_big[k] else dpool[pick[k]]
-            m_offered += g.m
-            t = srv.submit(g, slim.OP_TR, float(ps[k]), graphgen.mix_seed(int(rate), k))
-            with cv:
-                tickets.append(t)
-                cv.notify()
-        with cv:
-            done[0] = True
-            cv.notify()
+            srv.submit(g, slim.OP_TR, float(ps[k]), graphgen.mix_seed(int(rate), k))
         th.join()
         st = srv.stats()
         row = {"rate_jobs_per_s": rate, "jobs": njobs, "big_jobs": int(pick_big.sum()),

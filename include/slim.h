@@ -223,10 +223,13 @@ SLIM_API void slim_batch_free(slim_batch_t* b);
  *
  * Memory: a job holds (a) a device copy of its CSR if it was submitted from
  * host memory, (b) its output CSR, from admission until slim_result_release,
- * and (c) its share of its batch's workspace while the batch runs.  The sum
- * over admitted jobs stays within hbm_budget_bytes (up to alignment slack
- * of a few KiB per batch); device memory comes from a caching arena that
- * the server owns and frees at slim_serve_destroy.
+ * and (c) its share of its batch's workspace while the batch runs.  Jobs
+ * are admitted while the sum of these reservations (each rounded up to an
+ * allocation size class, the workspace share with 10% headroom) stays within
+ * hbm_budget_bytes.  Device memory comes from a caching arena that the
+ * server owns and frees at slim_serve_destroy; it reuses a cached block for
+ * any request of at least half its size and trims its cache to keep the
+ * memory it holds within 1.125 x the budget.
  */
 #define SLIM_HOST 0u   /* slim_job_t.where: CSR arrays in host memory */
 #define SLIM_DEVICE 1u /* slim_job_t.where: CSR arrays in device memory */
@@ -287,6 +290,14 @@ SLIM_API int slim_serve_submit(slim_server_t* s, const slim_job_t* job, uint64_t
 SLIM_API int slim_serve_poll(slim_server_t* s, uint64_t ticket, slim_result_t* res);
 /* Blocks until the job is finished, then as slim_serve_poll. */
 SLIM_API int slim_serve_wait(slim_server_t* s, uint64_t ticket, slim_result_t* res);
+/*
+ * Completion queue: returns the next finished job (in the order jobs finish)
+ * that this call has not returned before and that is not yet released, with
+ * its ticket.  timeout_ms < 0 waits without limit, 0 only looks; SLIM_EAGAIN
+ * when none finished in time.
+ */
+SLIM_API int slim_serve_next(slim_server_t* s, int64_t timeout_ms, uint64_t* ticket,
+                             slim_result_t* res);
 /* Drops a job that has not started (SLIM_OK); SLIM_EAGAIN once it runs. */
 SLIM_API int slim_serve_cancel(slim_server_t* s, uint64_t ticket);
 /* Copies a finished job's output CSR into caller memory (host or device;

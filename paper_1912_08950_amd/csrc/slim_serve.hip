@@ -41,20 +41,24 @@ uint64_t size_class(uint64_t bytes) {
   return (bytes + step - 1) / step * step;
 }
 
-// Caching device allocator.  Freed blocks are kept per size class and reused;
-// when live plus cached bytes would pass `cap`, cached blocks are freed first.
+// Caching device allocator.  Freed blocks are kept by size and reused for
+// any request of at least half their size (the smallest fitting block
+// first); only when live plus cached bytes would pass `cap` are cached blocks
+// freed (hipFree waits for the device, so this is kept rare).  A block's
+// size travels with it: alloc returns it in *got, free takes it back.
 class Arena {
  public:
   void set_cap(uint64_t cap) { cap_ = cap; }
-  void* alloc(uint64_t bytes) {
+  void* alloc(uint64_t bytes, uint64_t* got) {
     const uint64_t c = size_class(bytes);
     std::lock_guard<std::mutex> lk(mu_);
-    auto it = cache_.find(c);
-    if (it != cache_.end()) {
+    auto it = cache_.lower_bound(c);
+    if (it != cache_.end() && it->first <= 2 * c) {
       void* p = it->second;
+      *got = it->first;
+      cached_ -= it->first;
+      live_ += it->first;
       cache_.erase(it);
-      cached_ -= c;
-      live_ += c;
       return p;
     }
     while (live_ + cached_ + c > cap_ && !cache_.empty()) {
@@ -68,16 +72,16 @@ class Arena {
       (void)hipGetLastError();
       return nullptr;
     }
+    *got = c;
     live_ += c;
     return p;
   }
-  void free(void* p, uint64_t bytes) {
+  void free(void* p, uint64_t size) {
     if (!p) return;
-    const uint64_t c = size_class(bytes);
     std::lock_guard<std::mutex> lk(mu_);
-    cache_.emplace(c, p);
-    live_ -= c;
-    cached_ += c;
+    cache_.emplace(size, p);
+    live_ -= size;
+    cached_ += size;
   }
   void release_all() {
     std::lock_guard<std::mutex> lk(mu_);
@@ -100,10 +104,11 @@ struct Job {
   State state = kQueued;
   int status = SLIM_OK;
   uint64_t res_out = 0, res_in = 0, res_ws = 0;  // reserved bytes
-  void* in_row = nullptr;
+  void* in_row = nullptr;  // device buffers and the arena block sizes behind them
   void* in_col = nullptr;
   void* out_row = nullptr;
   void* out_col = nullptr;
+  uint64_t sz_in_row = 0, sz_in_col = 0, sz_out_row = 0, sz_out_col = 0;
   slim_stats_t stats{};
   double t_submit = 0, t_start = 0, t_done = 0;
 };
@@ -139,6 +144,7 @@ struct slim_server {
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<uint64_t> pending, ready;
+  std::deque<uint64_t> finished;  // completion order, consumed by slim_serve_next
   std::unordered_map<uint64_t, std::unique_ptr<Job>> jobs;
   uint64_t next_ticket = 1;
   uint64_t in_use = 0, peak = 0;
@@ -189,14 +195,14 @@ int run_batch(slim_server* S, Worker& W, const std::vector<Job*>& batch) {
   for (uint32_t i = 0; i < cnt; ++i) {
     Job* j = batch[i];
     const slim_job_t& J = j->spec;
-    j->out_row = S->arena.alloc(8 * (J.n + 1));
-    j->out_col = J.nnz ? S->arena.alloc(4 * J.nnz) : nullptr;
+    j->out_row = S->arena.alloc(8 * (J.n + 1), &j->sz_out_row);
+    j->out_col = J.nnz ? S->arena.alloc(4 * J.nnz, &j->sz_out_col) : nullptr;
     if (!j->out_row || (J.nnz && !j->out_col)) return fail(SLIM_EDEVICE, "serve: out of device memory");
     const int64_t* in_row = J.row_off;
     const uint32_t* in_col = J.col;
     if (J.where == SLIM_HOST) {
-      j->in_row = S->arena.alloc(8 * (J.n + 1));
-      j->in_col = J.nnz ? S->arena.alloc(4 * J.nnz) : nullptr;
+      j->in_row = S->arena.alloc(8 * (J.n + 1), &j->sz_in_row);
+      j->in_col = J.nnz ? S->arena.alloc(4 * J.nnz, &j->sz_in_col) : nullptr;
       if (!j->in_row || (J.nnz && !j->in_col)) return fail(SLIM_EDEVICE, "serve: out of device memory");
       if (hipMemcpyAsync(j->in_row, J.row_off, 8 * (J.n + 1), hipMemcpyHostToDevice, s) !=
               hipSuccess ||
@@ -223,7 +229,8 @@ int run_batch(slim_server* S, Worker& W, const std::vector<Job*>& batch) {
   const SetLayout L = set_layout(P.shape);
   const uint64_t stats_off = L.total;
   const uint64_t ws_bytes = L.total + sizeof(slim_stats_t) * cnt;
-  void* ws = S->arena.alloc(ws_bytes);
+  uint64_t ws_got = 0;
+  void* ws = S->arena.alloc(ws_bytes, &ws_got);
   if (!ws) return fail(SLIM_EDEVICE, "serve: out of device memory (workspace)");
   slim_stats_t* dstats = reinterpret_cast<slim_stats_t*>(static_cast<char*>(ws) + stats_off);
   for (uint32_t i = 0; i < cnt; ++i) P.gd[i].stats = dstats + i;
@@ -252,19 +259,19 @@ int run_batch(slim_server* S, Worker& W, const std::vector<Job*>& batch) {
     for (uint32_t i = 0; i < cnt; ++i)
       batch[i]->stats = static_cast<const slim_stats_t*>(W.pin_stats)[i];
   (void)hipStreamSynchronize(s);  // nothing may still use ws or the pinned buffers
-  S->arena.free(ws, ws_bytes);
+  S->arena.free(ws, ws_got);
   return rc;
 }
 
 void free_inputs(slim_server* S, Job* j) {
-  S->arena.free(j->in_row, 8 * (j->spec.n + 1));
-  S->arena.free(j->in_col, 4 * j->spec.nnz);
+  S->arena.free(j->in_row, j->sz_in_row);
+  S->arena.free(j->in_col, j->sz_in_col);
   j->in_row = j->in_col = nullptr;
 }
 
 void free_outputs(slim_server* S, Job* j) {
-  S->arena.free(j->out_row, 8 * (j->spec.n + 1));
-  S->arena.free(j->out_col, 4 * j->spec.nnz);
+  S->arena.free(j->out_row, j->sz_out_row);
+  S->arena.free(j->out_col, j->sz_out_col);
   j->out_row = j->out_col = nullptr;
 }
 
@@ -307,6 +314,7 @@ void worker_main(slim_server* S, int wi) {
         j->status = rc;
         j->state = kDone;
         j->t_done = t;
+        S->finished.push_back(j->ticket);
         if (rc == SLIM_OK) {
           ++S->completed;
           S->lat.push_back(t - j->t_submit);
@@ -438,6 +446,32 @@ int slim_serve_wait(slim_server_t* S, uint64_t ticket, slim_result_t* res) {
     }
     if (S->stop) return fail(SLIM_EINVAL, "server is shutting down");
     S->cv_done.wait(lk);
+  }
+}
+
+int slim_serve_next(slim_server_t* S, int64_t timeout_ms, uint64_t* ticket, slim_result_t* res) {
+  if (!S || !ticket || !res) return fail(SLIM_EINVAL, "NULL argument");
+  std::unique_lock<std::mutex> lk(S->mu);
+  const auto deadline =
+      std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms);
+  for (;;) {
+    while (!S->finished.empty()) {
+      const uint64_t t = S->finished.front();
+      S->finished.pop_front();
+      auto it = S->jobs.find(t);
+      if (it == S->jobs.end()) continue;  // released before it was taken here
+      *ticket = t;
+      fill_result(it->second.get(), res);
+      return ok();
+    }
+    if (S->stop) return fail(SLIM_EINVAL, "server is shutting down");
+    if (timeout_ms == 0) return SLIM_EAGAIN;
+    if (timeout_ms < 0) {
+      S->cv_done.wait(lk);
+    } else if (S->cv_done.wait_until(lk, deadline) == std::cv_status::timeout &&
+               S->finished.empty()) {
+      return SLIM_EAGAIN;
+    }
   }
 }
 

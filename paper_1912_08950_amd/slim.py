@@ -29,7 +29,7 @@ SYMBOLS = ("slim_last_error", "slim_strerror", "slim_version", "slim_load_csr",
            "slim_batch_create", "slim_batch_workspace_size", "slim_batch_run", "slim_batch_set",
            "slim_batch_get", "slim_batch_tune", "slim_batch_free",
            "slim_serve_create", "slim_serve_submit", "slim_serve_poll", "slim_serve_wait",
-           "slim_serve_cancel", "slim_serve_copy", "slim_result_release", "slim_serve_stats",
+           "slim_serve_next", "slim_serve_cancel", "slim_serve_copy", "slim_result_release", "slim_serve_stats",
            "slim_serve_reset_stats", "slim_serve_destroy",
            "slim_tune_set", "slim_tune_get", "slim_profile_enable", "slim_profile_read")
 
@@ -134,6 +134,8 @@ def _bind(path: str = LIB_PATH):
     for fn in (lib.slim_serve_poll, lib.slim_serve_wait):
         fn.restype = i32
         fn.argtypes = [vp, u64, ctypes.POINTER(Result)]
+    lib.slim_serve_next.restype = i32
+    lib.slim_serve_next.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(u64), ctypes.POINTER(Result)]
     lib.slim_serve_cancel.restype = i32
     lib.slim_serve_cancel.argtypes = [vp, u64]
     lib.slim_serve_copy.restype = i32
@@ -439,6 +441,17 @@ class Server:
         r = Result()
         _check(_lib.slim_serve_wait(self._h, ticket, ctypes.byref(r)))
         return r
+
+    def next(self, timeout_ms: int = -1):
+        """(ticket, Result) of the next job to finish, in completion order;
+        None if none finished within timeout_ms (-1: wait without limit)."""
+        r = Result()
+        t = ctypes.c_uint64(0)
+        rc = _lib.slim_serve_next(self._h, int(timeout_ms), ctypes.byref(t), ctypes.byref(r))
+        if rc == EAGAIN:
+            return None
+        _check(rc)
+        return int(t.value), r
 
     def cancel(self, ticket: int) -> bool:
         rc = _lib.slim_serve_cancel(self._h, ticket)

@@ -137,3 +137,25 @@ def test_serve_cancel_and_errors(slim):
     srv.reset_stats()
     assert srv.stats()["completed"] == 0
     srv.close()
+
+
+def test_serve_completion_queue(slim):
+    """slim_serve_next returns every finished job exactly once, in completion
+    order, and skips jobs released before it reached them."""
+    srv = slim.Server(16 << 30, n_streams=2)
+    gs = gg.batch_mix(12, 17, 1000, 5000)
+    ts = [srv.submit(g, slim.OP_TR, 0.5, i) for i, g in enumerate(gs)]
+    first = srv.wait(ts[0])
+    assert first.status == slim.OK
+    srv.release(ts[0])  # released before next() sees it
+    seen = []
+    while len(seen) < len(ts) - 1:
+        tr = srv.next(10000)
+        assert tr is not None
+        t, r = tr
+        assert r.status == slim.OK and t not in seen and t != ts[0]
+        seen.append(t)
+        srv.release(t)
+    assert sorted(seen) == sorted(ts[1:])
+    assert srv.next(0) is None
+    srv.close()
