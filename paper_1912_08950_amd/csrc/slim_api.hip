@@ -144,6 +144,7 @@ SetLayout set_layout(const SetShape& S) {
     L.kb = c.take<uint32_t>(n);
     L.vb = c.take<uint32_t>(n);
     L.rank = c.take<uint32_t>(n);
+    L.rcol = c.take<uint32_t>(S.NNZ);
     L.hist = c.take<uint32_t>(hist);
     L.hist_scan = c.take<uint64_t>(hist + 1);
     L.fstart = c.take<uint32_t>(n + 1);
@@ -264,7 +265,8 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
     uint32_t* fstart = at<uint32_t>(ws, L.fstart);
     uint32_t* dag_col = at<uint32_t>(ws, L.dag_col);
     uint2* dag_rng = at<uint2>(ws, L.dag_rng);
-    orient(row_off, col, rank, gu, t0u, recs_u, S.n_u, tile_cnt, tile_base, scan_tmp, s);
+    uint32_t* rcol = at<uint32_t>(ws, L.rcol);
+    orient(row_off, col, rank, rcol, gu, t0u, recs_u, S.n_u, tile_cnt, tile_base, scan_tmp, s);
     dag_ranges(order, fstart, S.N, dag_rng, s);
     sort_rows(dag_rng, S.N, dag_col, at<uint32_t>(ws, L.sort_lists),
               at<uint32_t>(ws, L.sort_counts), num_cu, s);
@@ -283,6 +285,7 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
     a.row_off = row_off;
     a.col = col;
     a.rank = rank;
+    a.rcol = rcol;
     a.order = order;
     a.dag_rng = dag_rng;
     a.fstart = fstart;

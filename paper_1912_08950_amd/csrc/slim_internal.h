@@ -71,8 +71,9 @@ void gather(const GDesc* gd, uint32_t count, const uint64_t* vtile0, const uint6
             uint64_t nvt, uint64_t net, uint64_t N, uint64_t NNZ, int64_t* urow, uint32_t* ucol,
             hipStream_t s);
 
-// DAG: dag_col = rank ids of the forward entries, fstart = row starts.
-void orient(const int64_t* row_off, const uint32_t* col, const uint32_t* rank,
+// DAG: dag_col = rank ids of the forward entries, fstart = row starts;
+// rcol[j] = rank of col[j] for every entry.
+void orient(const int64_t* row_off, const uint32_t* col, const uint32_t* rank, uint32_t* rcol,
             const GDesc* gd_union, const uint64_t* tile0, const TileRec* recs, uint64_t ntiles,
             uint32_t* tile_cnt, uint64_t* tile_base, uint64_t* scan_tmp, hipStream_t s);
 void dag_ranges(const uint32_t* order, const uint32_t* fstart, uint64_t n, uint2* dag_rng,
@@ -104,6 +105,7 @@ struct TriArgs {
   const int64_t* row_off;
   const uint32_t* col;
   const uint32_t* rank;
+  const uint32_t* rcol;    // rank id of every CSR column
   const uint32_t* order;
   const uint2* dag_rng;    // DAG row of each rank id
   const uint32_t* fstart;  // DAG row start of each union id (N+1)

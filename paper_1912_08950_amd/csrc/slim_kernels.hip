@@ -4,6 +4,7 @@
 // Data layout (all in HBM, caller-provided workspace), over the union CSR of
 // the set (n vertices, nnz entries, m = nnz/2 edges):
 //   rank[n], order[n]   union id -> rank id and back; rank order = (degree, id)
+//   rcol[nnz]           rank id of every CSR column (streamed by the orientation)
 //   dag_col[m]          rank ids of the higher-ranked neighbours, rows laid
 //                       out in union-id row order (a stream compaction of CSR)
 //   dag_rng[n]          (begin, end) of row x of the DAG, indexed by rank id
@@ -414,16 +415,32 @@ __device__ __forceinline__ uint32_t tile_row_of(const TileRows& L, int i) {
 // Policies decide per CSR entry j (union row r) whether it is kept and what
 // is written; kept entries keep their CSR order, so rows stay sorted.  A
 // policy's Ctx holds what it needs of the tile's graph.
-struct OrientPolicy {  // keep (r,c) iff rank(c) > rank(r); write rank(c)
+// Orientation: keep (r,c) iff rank(c) > rank(r) and write rank(c).  The
+// counting pass gathers rank(c) once per entry and streams it to rcol; the
+// scatter pass and the triangle kernel read rcol instead of gathering.
+struct OrientCountPolicy {
   const uint32_t* col;
   const uint32_t* rank;
+  uint32_t* rcol;
   struct Ctx {};
   __device__ Ctx ctx(const GDesc&) const { return {}; }
   __device__ bool needs_rows(const GDesc&) const { return true; }
   __device__ bool flag(const Ctx&, uint64_t j, uint32_t r) const {
-    return rank[col[j]] > rank[r];
+    const uint32_t rc = rank[col[j]];
+    rcol[j] = rc;
+    return rc > rank[r];
   }
   __device__ uint32_t value(const Ctx&, uint64_t j) const { return rank[col[j]]; }
+};
+
+struct OrientScatterPolicy {
+  const uint32_t* rcol;
+  const uint32_t* rank;
+  struct Ctx {};
+  __device__ Ctx ctx(const GDesc&) const { return {}; }
+  __device__ bool needs_rows(const GDesc&) const { return true; }
+  __device__ bool flag(const Ctx&, uint64_t j, uint32_t r) const { return rcol[j] > rank[r]; }
+  __device__ uint32_t value(const Ctx&, uint64_t j) const { return rcol[j]; }
 };
 
 // Output of a compression job, per graph: a TR graph keeps (r,c) iff its
@@ -551,23 +568,27 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(P p, const int64_t* 
   }
 }
 
-template <class P, typename OffT>
-void compact(const P& p, const int64_t* row_off, const GDesc* gd, const uint64_t* tile0,
-             const TileRec* recs, uint64_t ntiles, uint32_t* tile_cnt, uint64_t* tile_base,
-             uint64_t* scan_tmp, hipStream_t s) {
-  hipLaunchKernelGGL(k_compact_count<P>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, p, row_off,
-                     gd, recs, tile_cnt);
+// Count (policy Pc), scan, scatter (policy Ps): both policies flag the same
+// entries.
+template <class Pc, class Ps, typename OffT>
+void compact(const Pc& pc, const Ps& ps, const int64_t* row_off, const GDesc* gd,
+             const uint64_t* tile0, const TileRec* recs, uint64_t ntiles, uint32_t* tile_cnt,
+             uint64_t* tile_base, uint64_t* scan_tmp, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact_count<Pc>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, pc,
+                     row_off, gd, recs, tile_cnt);
   scan_excl<uint32_t>(tile_cnt, ntiles, tile_base, scan_tmp, s);
-  hipLaunchKernelGGL((k_compact_scatter<P, OffT>), dim3((unsigned)ntiles), dim3(kBlock), 0, s, p,
-                     row_off, gd, tile0, recs, (const uint64_t*)tile_base);
+  hipLaunchKernelGGL((k_compact_scatter<Ps, OffT>), dim3((unsigned)ntiles), dim3(kBlock), 0, s,
+                     ps, row_off, gd, tile0, recs, (const uint64_t*)tile_base);
 }
 
-void orient(const int64_t* row_off, const uint32_t* col, const uint32_t* rank,
+void orient(const int64_t* row_off, const uint32_t* col, const uint32_t* rank, uint32_t* rcol,
             const GDesc* gd_union, const uint64_t* tile0, const TileRec* recs, uint64_t ntiles,
             uint32_t* tile_cnt, uint64_t* tile_base, uint64_t* scan_tmp, hipStream_t s) {
-  OrientPolicy p{col, rank};
-  compact<OrientPolicy, uint32_t>(p, row_off, gd_union, tile0, recs, ntiles, tile_cnt, tile_base,
-                                  scan_tmp, s);
+  OrientCountPolicy pc{col, rank, rcol};
+  OrientScatterPolicy ps{rcol, rank};
+  compact<OrientCountPolicy, OrientScatterPolicy, uint32_t>(pc, ps, row_off, gd_union, tile0, recs,
+                                                            ntiles, tile_cnt, tile_base, scan_tmp,
+                                                            s);
 }
 
 __global__ void k_dag_rng(const uint32_t* order, const uint32_t* fstart, uint64_t n,
@@ -590,8 +611,8 @@ void compact_out(const int64_t* row_off, const uint32_t* col, const uint32_t* ei
                  const TileRec* recs, uint64_t ntiles, uint32_t* tile_cnt, uint64_t* tile_base,
                  uint64_t* scan_tmp, hipStream_t s) {
   OutPolicy p{col, eid, del, m};
-  compact<OutPolicy, int64_t>(p, row_off, gd, tile0, recs, ntiles, tile_cnt, tile_base,
-                              scan_tmp, s);
+  compact<OutPolicy, OutPolicy, int64_t>(p, p, row_off, gd, tile0, recs, ntiles, tile_cnt,
+                                         tile_base, scan_tmp, s);
 }
 
 // --------------------------------------------------------------- stats

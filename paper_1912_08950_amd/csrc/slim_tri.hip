@@ -190,7 +190,7 @@ __device__ void tri_forward_eids(TriCtx& C, TriSmem& S, uint32_t ia, uint32_t ib
   for (uint32_t i = ia + threadIdx.x; i < ib; i += kTB) {
     if (!(S.fwd[i >> 5] & (1u << (i & 31)))) continue;
     const uint64_t j = (uint64_t)C.j0 + i;
-    const uint32_t w = C.a.rank[C.a.col[j]];
+    const uint32_t w = C.a.rcol[j];
     const uint32_t xb = all_rows ? C.a.fstart[S.srow[i]] - C.D0 : 0u;
     uint32_t qpos;
     if (hlookup(S.hb, w, xb, qpos)) C.a.eid[j] = C.D0 + qpos;
@@ -248,7 +248,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     const uint64_t j = (uint64_t)C.j0 + i;
     const uint32_t r = S.srow[i];
     const uint32_t c = C.a.col[j];
-    const uint32_t y = C.a.rank[c];
+    const uint32_t y = C.a.rcol[j];
     const uint32_t x = C.a.rank[r];
     const uint2 yr = C.a.dag_rng[y];
     const uint32_t fs = C.a.fstart[r], fe = C.a.fstart[r + 1];
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
       const uint32_t i = c * kWave + lane;
       bool f = false, g = false;
       if (i < span) {
-        const uint32_t rc = a.rank[a.col[j0 + i]], rr = a.rank[S.srow[i]];
+        const uint32_t rc = a.rcol[j0 + i], rr = a.rank[S.srow[i]];
         f = rc < rr;
         g = rc > rr;
       }
