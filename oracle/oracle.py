@@ -52,6 +52,8 @@ def _load():
     for fn in (lib.orc_triangle_reduce, lib.orc_edge_sample):
         fn.argtypes = [u64, vp, vp, dbl, u64, vp, vp, vp]
         fn.restype = ctypes.c_int
+    lib.orc_triangle_reduce_x.argtypes = [u64, vp, vp, dbl, u64, ctypes.c_int, vp, vp, vp]
+    lib.orc_triangle_reduce_x.restype = ctypes.c_int
     lib.orc_tr_rows.argtypes = [u64, vp, vp, dbl, u64, vp, u64, vp, vp]
     lib.orc_tr_rows.restype = ctypes.c_int
     lib.orc_edge_triangle_counts.argtypes = [u64, vp, vp, vp]
@@ -119,6 +121,18 @@ def _run(fn, g, p, seed):
 def triangle_reduce(g, p: float, seed: int):
     """Triangle p-1-Reduction of CSR ``g``: (row_off, col, stats)."""
     return _run(_load().orc_triangle_reduce, g, p, seed)
+
+
+def triangle_reduce_x(g, p: float, seed: int, variant: int):
+    """Triangle p-x-Reduction variants: 1 = p-1, 2 = p-2 (a selected triangle
+    keeps one uniform edge), 3 = Min-Count p-1 (removes its edge in the fewest
+    input triangles, ties uniform).  Returns (row_off, col, stats)."""
+    lib = _load()
+
+    def fn(n, ro, col, p_, seed_, oro, ocol, st):
+        return lib.orc_triangle_reduce_x(n, ro, col, p_, seed_, int(variant), oro, ocol, st)
+
+    return _run(fn, g, p, seed)
 
 
 def edge_sample(g, p: float, seed: int):

@@ -29,6 +29,13 @@
  *       kernel instances run once, concurrently (section 4.5, runtime
  *       listing `lst:general`: a single `run_kernels` pass); deleting an
  *       already deleted edge is a no-op.
+ *   R5  Triangle p-2-Reduction (section 4.3: x in {1,2} edges of a selected
+ *       triangle are removed, chosen u.a.r.): the two removed edges are the
+ *       ones other than edge k of R4, i.e. the kept edge is uniform.
+ *   R6  Min-Count Triangle p-1-Reduction (section 4.3): t_e = triangles of
+ *       the input graph that contain e; a selected triangle removes its
+ *       edge of smallest t_e, ties broken uniformly by word x1 among the
+ *       tied edges in the order of R4.
  *   R4  The random source `SG.rand` is unspecified in the paper; here it is
  *       Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
  *       key = (seed mod 2^32, seed div 2^32).  For the triangle {a<b<c}
@@ -93,6 +100,9 @@ int orc_threshold(double p, uint64_t* thr) {
     *thr = (uint64_t)floor(p * 4294967296.0);
   return 0;
 }
+
+int orc_edge_triangle_counts(uint64_t n, const int64_t* row_off, const uint32_t* col,
+                             uint32_t* t);
 
 /* ------------------------------------------------------ graph helpers */
 
@@ -317,6 +327,107 @@ int orc_triangle_reduce(uint64_t n, const int64_t* row_off, const uint32_t* col,
   for (uint64_t j = 0; j < nnz; ++j) deleted += c.del[j];
   orc_compact(&g, c.del, out_row_off, out_col);
   free(c.del);
+  stats[0] = n;
+  stats[1] = nnz / 2;
+  stats[2] = c.T;
+  stats[3] = c.selected;
+  stats[4] = deleted;
+  stats[5] = nnz / 2 - deleted;
+  return 0;
+}
+
+/* ------------------------------- Triangle p-x-Reduction variants (4.3)
+ * variant 1: p-1 (as orc_triangle_reduce); variant 2: Triangle
+ * p-2-Reduction, where a selected triangle loses x = 2 of its edges chosen
+ * uniformly, i.e. keeps the one edge k = floor(x1 * 3 / 2^32) and loses the
+ * other two (R5); variant 3: Min-Count Triangle p-1-Reduction, where a
+ * selected triangle loses the edge that lies in the fewest triangles of the
+ * input graph, ties broken uniformly: among the tied edges, in the order
+ * {a,b}, {a,c}, {b,c}, the one at index floor(x1 * ties / 2^32) (R6).
+ * stats as orc_triangle_reduce.
+ */
+typedef struct {
+  const orc_graph* g;
+  uint64_t thr;
+  uint32_t key[2];
+  int variant;
+  const uint32_t* tcount; /* variant 3: triangles per CSR entry */
+  uint8_t* del;
+  uint64_t T, selected;
+  int err;
+} orc_trx_ctx;
+
+static void orc_trx_cb(void* vctx, uint32_t x, uint32_t y, uint32_t z) {
+  orc_trx_ctx* c = (orc_trx_ctx*)vctx;
+  orc_sort3(&x, &y, &z);
+  uint32_t ctr[4] = {x, y, z, 0u};
+  uint32_t r[4];
+  orc_philox4x32_10(ctr, c->key, r);
+  c->T++;
+  if ((uint64_t)r[0] >= c->thr) return;
+  c->selected++;
+  /* the three edges in the fixed order {x,y}, {x,z}, {y,z} */
+  int64_t slot[3] = {orc_edge_slot(c->g, x, y), orc_edge_slot(c->g, x, z),
+                     orc_edge_slot(c->g, y, z)};
+  if (slot[0] < 0 || slot[1] < 0 || slot[2] < 0) {
+    c->err = 1;
+    return;
+  }
+  if (c->variant == 3) {
+    uint32_t t[3], tmin;
+    for (int e = 0; e < 3; ++e) t[e] = c->tcount[slot[e]];
+    tmin = t[0];
+    if (t[1] < tmin) tmin = t[1];
+    if (t[2] < tmin) tmin = t[2];
+    int tied[3], nt = 0;
+    for (int e = 0; e < 3; ++e)
+      if (t[e] == tmin) tied[nt++] = e;
+    uint32_t pick = (uint32_t)(((uint64_t)r[1] * (uint64_t)nt) >> 32);
+    c->del[slot[tied[pick]]] = 1;
+  } else {
+    uint32_t k = (uint32_t)(((uint64_t)r[1] * 3u) >> 32);
+    for (int e = 0; e < 3; ++e) {
+      int hit = c->variant == 2 ? e != (int)k : e == (int)k;
+      if (hit) c->del[slot[e]] = 1;
+    }
+  }
+}
+
+int orc_triangle_reduce_x(uint64_t n, const int64_t* row_off, const uint32_t* col, double p,
+                          uint64_t seed, int variant, int64_t* out_row_off, uint32_t* out_col,
+                          uint64_t* stats) {
+  if (variant < 1 || variant > 3) return -4;
+  orc_graph g = {n, row_off, col};
+  uint64_t nnz = (uint64_t)row_off[n];
+  orc_trx_ctx c;
+  memset(&c, 0, sizeof(c));
+  if (orc_threshold(p, &c.thr)) return -1;
+  c.g = &g;
+  c.key[0] = (uint32_t)seed;
+  c.key[1] = (uint32_t)(seed >> 32);
+  c.variant = variant;
+  c.del = (uint8_t*)calloc(nnz > 0 ? nnz : 1, 1);
+  uint32_t* tc = NULL;
+  if (!c.del) return -2;
+  if (variant == 3) {
+    tc = (uint32_t*)malloc((nnz > 0 ? nnz : 1) * sizeof(uint32_t));
+    if (!tc) {
+      free(c.del);
+      return -2;
+    }
+    orc_edge_triangle_counts(n, row_off, col, tc);
+    c.tcount = tc;
+  }
+  if (orc_for_each_triangle(&g, orc_trx_cb, &c) || c.err) {
+    free(c.del);
+    free(tc);
+    return -3;
+  }
+  uint64_t deleted = 0;
+  for (uint64_t j = 0; j < nnz; ++j) deleted += c.del[j];
+  orc_compact(&g, c.del, out_row_off, out_col);
+  free(c.del);
+  free(tc);
   stats[0] = n;
   stats[1] = nnz / 2;
   stats[2] = c.T;

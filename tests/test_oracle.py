@@ -332,3 +332,139 @@ def test_determinism(cfg1):
     c = O.triangle_reduce(cfg1, 0.5, 43)
     assert np.array_equal(a[1], b[1]) and a[2] == b[2]
     assert not np.array_equal(a[1], c[1])
+
+
+# ------------------------------- Triangle p-2 and Min-Count p-1 variants
+
+def brute_reduce_x(g, p, seed, variant):
+    """The variants written out on tiny graphs with sets: O(n^3) triangles,
+    per-edge counts from the triangle list, selection and edge choice from
+    the Philox words (Philox itself is pinned by the known-answer vectors)."""
+    thr = O.threshold(p)
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    tris = sorted(brute_triangles(g))
+    count = {}
+    for x, y, z in tris:
+        for e in ((x, y), (x, z), (y, z)):
+            count[e] = count.get(e, 0) + 1
+    dele, sel = set(), 0
+    for x, y, z in tris:
+        w = O.philox4x32_10((x, y, z, 0), key)
+        if w[0] >= thr:
+            continue
+        sel += 1
+        edges = [(x, y), (x, z), (y, z)]
+        if variant == 3:
+            tmin = min(count[e] for e in edges)
+            tied = [e for e in edges if count[e] == tmin]
+            dele.add(tied[(w[1] * len(tied)) >> 32])
+        else:
+            k = (w[1] * 3) >> 32
+            dele |= {e for i, e in enumerate(edges) if (i != k) == (variant == 2)}
+    keep = undirected(g.row_off, g.col) - dele
+    return keep, len(tris), sel, len(dele)
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("n,q,seed", [(9, 0.6, 1), (12, 0.5, 2), (14, 0.45, 3), (10, 0.8, 4)])
+def test_reduce_x_matches_brute_force(variant, n, q, seed):
+    g = gg.er(n, q * (n - 1), seed)
+    for p, s in ((1.0, 7), (0.5, 8), (0.7, 2**40 + 3)):
+        ro, col, st = O.triangle_reduce_x(g, p, s, variant)
+        keep, t, sel, nd = brute_reduce_x(g, p, s, variant)
+        assert undirected(ro, col) == keep and is_valid_csr(g.n, ro, col)
+        assert (st["T"], st["selected"], st["deleted"]) == (t, sel, nd)
+
+
+def test_reduce_x_variant1_is_p1(cfg1):
+    for p, s in ((0.5, 1), (0.2, 9), (1.0, 3)):
+        a, b = O.triangle_reduce(cfg1, p, s), O.triangle_reduce_x(cfg1, p, s, 1)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
+def test_p2_and_p1_split_a_triangle():
+    """On K3 with p = 1 the same draw deletes edge k under p-1 and the other
+    two under p-2: together every edge, never one twice."""
+    g = gg.complete(3)
+    full = undirected(g.row_off, g.col)
+    for s in range(50):
+        r1, c1, _ = O.triangle_reduce_x(g, 1.0, s, 1)
+        r2, c2, st2 = O.triangle_reduce_x(g, 1.0, s, 2)
+        d1, d2 = full - undirected(r1, c1), full - undirected(r2, c2)
+        assert len(d1) == 1 and len(d2) == 2 and not (d1 & d2) and (d1 | d2) == full
+        assert st2["m_out"] == 1
+
+
+def test_p2_kept_edge_is_uniform():
+    g = gg.complete(3)
+    counts = {}
+    for s in range(600):
+        ro, col, _ = O.triangle_reduce_x(g, 1.0, s, 2)
+        e = next(iter(undirected(ro, col)))
+        counts[e] = counts.get(e, 0) + 1
+    chi2 = sum((c - 200) ** 2 / 200 for c in counts.values())
+    assert len(counts) == 3 and chi2 < 16.3  # chi-square, 2 dof, p ~ 3e-4
+
+
+def test_p2_edge_disjoint_triangles():
+    """Friendship graph F_k (k edge-disjoint triangles): p-2 deletes exactly
+    two edges per selected triangle; p = 1 keeps one edge of each."""
+    g = gg.friendship(200)
+    for s in range(5):
+        _, _, st = O.triangle_reduce_x(g, 0.6, s, 2)
+        assert st["deleted"] == 2 * st["selected"]
+    assert O.triangle_reduce_x(g, 1.0, 1, 2)[2]["m_out"] == 200
+
+
+def test_p2_expected_deletions_exact():
+    """E[|D|] = sum_e 1 - (1 - 2p/3)^{t_e} for p-2 (t_e from dense A^2)."""
+    g = gg.er(300, 60.0, 5)
+    a = dense(g).astype(np.float64)
+    te = (a @ a)[np.triu_indices(g.n, 1)][a[np.triu_indices(g.n, 1)] > 0]
+    for p in (0.2, 0.5):
+        expect = float(np.sum(1.0 - (1.0 - 2 * p / 3.0) ** te))
+        var_ub = float(np.sum((1.0 - 2 * p / 3.0) ** te * (1.0 - (1.0 - 2 * p / 3.0) ** te)))
+        ds = [O.triangle_reduce_x(g, p, s, 2)[2]["deleted"] for s in range(40)]
+        assert abs(np.mean(ds) - expect) < 6 * math.sqrt(3 * var_ub / len(ds)) + 1, (p, expect)
+
+
+@pytest.mark.parametrize("g", [gg.friendship(150), gg.complete(4), gg.complete(9)],
+                         ids=["friendship150", "K4", "K9"])
+def test_min_count_equals_p1_when_counts_are_equal(g):
+    """Every edge in the same number of triangles: all three tie, the uniform
+    tie-break picks index floor(x1*3/2^32) -- exactly the p-1 choice."""
+    for p, s in ((0.5, 1), (1.0, 2), (0.3, 3)):
+        a, b = O.triangle_reduce(g, p, s), O.triangle_reduce_x(g, p, s, 3)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
+def test_min_count_diamond_keeps_the_shared_edge():
+    """Two triangles {0,1,2}, {1,2,3} share {1,2} (in 2 triangles; the others
+    in 1): with p = 1 the shared edge always survives and each triangle loses
+    one of its own edges."""
+    g = gg.from_pairs(4, [(0, 1), (0, 2), (1, 2), (1, 3), (2, 3)])
+    for s in range(40):
+        ro, col, st = O.triangle_reduce_x(g, 1.0, s, 3)
+        kept = undirected(ro, col)
+        assert (1, 2) in kept and st["deleted"] == 2 and len(kept) == 3
+
+
+def test_min_count_deletes_only_minimal_edges(cfg1):
+    """Each deleted edge has the smallest triangle count among the edges of
+    some triangle containing it (counts from the per-edge merge oracle)."""
+    ro_in, col_in = cfg1.row_off, cfg1.col
+    t = O.edge_triangle_counts(cfg1)
+    cnt = {}
+    for r in range(cfg1.n):
+        for j in range(ro_in[r], ro_in[r + 1]):
+            cnt[(r, int(col_in[j]))] = int(t[j])
+    tris = O.list_triangles(cfg1)
+    ro, col, st = O.triangle_reduce_x(cfg1, 1.0, 5, 3)
+    deleted = undirected(ro_in, col_in) - undirected(ro, col)
+    ok = set()
+    for x, y, z in tris:
+        es = [(int(x), int(y)), (int(x), int(z)), (int(y), int(z))]
+        tmin = min(cnt[e] for e in es)
+        ok |= {e for e in es if cnt[e] == tmin}
+    assert deleted and deleted <= ok
+    assert st["deleted"] <= st["selected"] == st["T"]
