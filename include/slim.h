@@ -79,8 +79,10 @@ SLIM_API int slim_load_csr(const int64_t* d_row_off, const uint32_t* d_col, uint
 SLIM_API void slim_graph_free(slim_graph_t* g);
 
 /* ------------------------------------------------- compression calls */
-#define SLIM_OP_TR 1 /* Triangle p-1-Reduction */
-#define SLIM_OP_ES 2 /* uniform edge sampling */
+#define SLIM_OP_TR 1   /* Triangle p-1-Reduction */
+#define SLIM_OP_ES 2   /* uniform edge sampling */
+#define SLIM_OP_TR2 3  /* Triangle p-2-Reduction */
+#define SLIM_OP_MCTR 4 /* Min-Count Triangle p-1-Reduction */
 
 /* Device workspace (bytes) that `op` needs on graph `g`. */
 SLIM_API int slim_workspace_size(const slim_graph_t* g, int op, uint64_t* bytes);
@@ -134,6 +136,24 @@ SLIM_API int slim_edge_sample(const slim_graph_t* g, double p, uint64_t seed, vo
                      uint64_t ws_bytes, int64_t* d_out_row_off, uint32_t* d_out_col,
                      slim_stats_t* d_stats, void* stream);
 
+/*
+ * Any of the operations above by op code, with the arguments, layout and
+ * errors of slim_triangle_reduce (workspace: slim_workspace_size(g, op)).
+ *   SLIM_OP_TR    as slim_triangle_reduce.
+ *   SLIM_OP_ES    as slim_edge_sample.
+ *   SLIM_OP_TR2   Triangle p-2-Reduction (section 4.3, x = 2): a selected
+ *                 triangle loses two edges chosen uniformly -- every edge
+ *                 except k of slim_triangle_reduce's draw.
+ *   SLIM_OP_MCTR  Min-Count Triangle p-1-Reduction (section 4.3): t_e =
+ *                 triangles of the input graph on edge e; a selected
+ *                 triangle loses its edge of smallest t_e; among tied edges
+ *                 (in the order {a,b}, {a,c}, {b,c}) the one at index
+ *                 floor(word1 * ties / 2^32).
+ */
+SLIM_API int slim_compress(const slim_graph_t* g, int op, double p, uint64_t seed, void* d_ws,
+                           uint64_t ws_bytes, int64_t* d_out_row_off, uint32_t* d_out_col,
+                           slim_stats_t* d_stats, void* stream);
+
 /* ------------------------------------------------------------ batches
  * Many graphs in one launch sequence: the graphs are gathered into one
  * union CSR in the workspace (graph g's vertex and entry ranges follow
@@ -152,9 +172,9 @@ SLIM_API int slim_edge_sample(const slim_graph_t* g, double p, uint64_t seed, vo
  * refreshes with one host-to-device copy when they change).
  */
 typedef struct slim_job_params {
-  int32_t op;    /* SLIM_OP_TR or SLIM_OP_ES */
+  int32_t op;    /* SLIM_OP_TR, SLIM_OP_ES, SLIM_OP_TR2 or SLIM_OP_MCTR */
   int32_t pad;   /* must be 0 */
-  double p;      /* as slim_triangle_reduce / slim_edge_sample */
+  double p;      /* as slim_compress */
   uint64_t seed; /* as slim_triangle_reduce / slim_edge_sample */
 } slim_job_params_t;
 
@@ -243,7 +263,7 @@ typedef struct slim_serve_cfg {
 } slim_serve_cfg_t;
 
 typedef struct slim_job {
-  int32_t op;           /* SLIM_OP_TR or SLIM_OP_ES */
+  int32_t op;           /* an op code of slim_compress */
   int32_t pad;          /* must be 0 */
   double p;             /* as slim_triangle_reduce / slim_edge_sample */
   uint64_t seed;

@@ -93,13 +93,15 @@ uint64_t tiles_of(uint64_t ne, uint64_t tile) {
   return t < 1 ? 1 : t;
 }
 
-SetShape single_shape(uint64_t n, uint64_t nnz, bool tr) {
+SetShape single_shape(uint64_t n, uint64_t nnz, int op) {
   SetShape S;
   S.count = 1;
   S.N = n;
   S.NNZ = nnz;
   S.gathered = false;
-  S.has_tr = tr;
+  S.has_tr = op_lists_triangles((uint32_t)op);
+  S.general = op == SLIM_OP_TR2 || op == SLIM_OP_MCTR;
+  S.has_mc = op == SLIM_OP_MCTR;
   S.n_c = tiles_of(nnz, kTile);
   S.n_u = S.n_c;
   for (int i = 0; i < 3; ++i) S.n_tri[i] = tiles_of(nnz, kTriTileMin << i);
@@ -156,6 +158,7 @@ SetLayout set_layout(const SetShape& S) {
     L.sort_lists = c.take<uint32_t>(3 * n);
     L.sort_counts = c.take<uint32_t>(4);
     L.tri_ctr = c.take<uint32_t>(4);
+    if (S.has_mc) L.tcount = c.take<uint32_t>(m);
   }
   L.scan_tmp = c.take<uint64_t>(st + 1);
   L.total = c.off;
@@ -296,8 +299,16 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
     a.gd = gd;
     a.recs = recs_t;
     a.ntiles = n_t;
-    triangles(a, at<uint32_t>(ws, L.tri_ctr), num_cu, knobs.tri_blocks_per_cu, knobs.tri_chunk,
-              s);
+    a.tcount = S.has_mc ? at<uint32_t>(ws, L.tcount) : nullptr;
+    if (S.has_mc) {  // Min-Count: per-edge triangle counts first
+      fill_u32(a.tcount, S.NNZ / 2, 0, s);
+      a.pass = 0;
+      triangles(a, true, at<uint32_t>(ws, L.tri_ctr), num_cu, knobs.tri_blocks_per_cu,
+                knobs.tri_chunk, s);
+    }
+    a.pass = 1;
+    triangles(a, S.general, at<uint32_t>(ws, L.tri_ctr), num_cu, knobs.tri_blocks_per_cu,
+              knobs.tri_chunk, s);
     prof_end(profile, s);
     prof_begin(profile, "compact", s);
   }
@@ -383,9 +394,12 @@ static_assert(sizeof(GDesc) == 104, "descriptor size");
 
 int single_op(int op, const slim_graph* g, double p, uint64_t seed, void* ws, uint64_t ws_bytes,
               int64_t* out_ro, uint32_t* out_col, slim_stats_t* stats, hipStream_t s) {
-  const bool tr = op == SLIM_OP_TR;
-  const char* what = tr ? "slim_triangle_reduce" : "slim_edge_sample";
-  const SetShape S = g ? single_shape(g->n, g->nnz, tr) : SetShape{};
+  if (!op_valid(op)) return fail(SLIM_EINVAL, "unknown op %d", op);
+  const bool tr = op_lists_triangles((uint32_t)op);
+  const char* what = op == SLIM_OP_TR ? "slim_triangle_reduce"
+                     : op == SLIM_OP_ES ? "slim_edge_sample"
+                                        : "slim_compress";
+  const SetShape S = g ? single_shape(g->n, g->nnz, op) : SetShape{};
   const uint64_t need = g && g->nnz ? set_layout(S).total : 0;
   if (int rc = check_call(g, p, ws, ws_bytes, need, out_ro, out_col)) return rc;
   (void)hipGetLastError();
@@ -528,8 +542,8 @@ void slim_graph_free(slim_graph_t* g) { delete g; }
 
 int slim_workspace_size(const slim_graph_t* g, int op, uint64_t* bytes) {
   if (!g || !bytes) return fail(SLIM_EINVAL, "NULL argument");
-  if (op != SLIM_OP_TR && op != SLIM_OP_ES) return fail(SLIM_EINVAL, "unknown op %d", op);
-  *bytes = g->nnz ? set_layout(single_shape(g->n, g->nnz, op == SLIM_OP_TR)).total : 0;
+  if (!op_valid(op)) return fail(SLIM_EINVAL, "unknown op %d", op);
+  *bytes = g->nnz ? set_layout(single_shape(g->n, g->nnz, op)).total : 0;
   return ok();
 }
 
@@ -537,6 +551,13 @@ int slim_triangle_reduce(const slim_graph_t* g, double p, uint64_t seed, void* d
                          uint64_t ws_bytes, int64_t* d_out_row_off, uint32_t* d_out_col,
                          slim_stats_t* d_stats, void* stream) {
   return single_op(SLIM_OP_TR, g, p, seed, d_ws, ws_bytes, d_out_row_off, d_out_col, d_stats,
+                   static_cast<hipStream_t>(stream));
+}
+
+int slim_compress(const slim_graph_t* g, int op, double p, uint64_t seed, void* d_ws,
+                  uint64_t ws_bytes, int64_t* d_out_row_off, uint32_t* d_out_col,
+                  slim_stats_t* d_stats, void* stream) {
+  return single_op(op, g, p, seed, d_ws, ws_bytes, d_out_row_off, d_out_col, d_stats,
                    static_cast<hipStream_t>(stream));
 }
 

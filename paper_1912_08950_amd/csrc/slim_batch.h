@@ -24,7 +24,9 @@ struct SetShape {
   uint32_t count = 0;
   uint64_t N = 0, NNZ = 0;  // union vertices and CSR entries
   bool gathered = false;    // union built in the workspace (batches)
-  bool has_tr = false;      // some graph runs Triangle p-1-Reduction
+  bool has_tr = false;      // some graph lists triangles (TR, TR2, MCTR)
+  bool general = false;     // some graph runs TR2 or MCTR (general triangle kernel)
+  bool has_mc = false;      // some graph runs MCTR (counting pass)
   uint64_t n_c = 0;         // graph-aligned tiles of kTile entries (compaction)
   uint64_t n_u = 0;         // union tiles of kTile entries (orientation)
   uint64_t n_tri[3] = {0, 0, 0};  // graph-aligned triangle tiles of 256, 512, 1024 entries
@@ -41,7 +43,7 @@ struct SetLayout {
   uint64_t tile_cnt, tile_base, scan_tmp;
   uint64_t ka, va, kb, vb, rank, rcol, hist, hist_scan;
   uint64_t fstart, dag_rng, dag_col, eid, del, counters;
-  uint64_t sort_lists, sort_counts, tri_ctr;
+  uint64_t sort_lists, sort_counts, tri_ctr, tcount;
   uint64_t total;
 };
 

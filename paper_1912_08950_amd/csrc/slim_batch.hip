@@ -42,7 +42,9 @@ int plan_set(const std::vector<GDesc>& graphs, SetPlan& P) {
     for (int i = 0; i < 3; ++i) S.n_tri[i] += tiles_of(d.ne, kTriTileMin << i);
     S.nvt += (d.nv + kTile - 1) / kTile;
     S.net += (d.ne + kTile - 1) / kTile;
-    if (d.op == SLIM_OP_TR) S.has_tr = true;
+    if (op_lists_triangles(d.op)) S.has_tr = true;
+    if (d.op == SLIM_OP_TR2 || d.op == SLIM_OP_MCTR) S.general = true;
+    if (d.op == SLIM_OP_MCTR) S.has_mc = true;
     uint64_t md = d.nv > 0 ? d.nv - 1 : 0;
     if (d.ne < md) md = d.ne;
     if (md > maxdeg) maxdeg = md;
@@ -263,7 +265,7 @@ int slim_batch_create(const slim_graph_t* const* graphs, const slim_job_params_t
     if (!G) return fail(SLIM_EINVAL, "graphs[%u] is NULL", g);
     if (G->device != dev)
       return fail(SLIM_EINVAL, "graphs[%u] lives on device %d, not %d", g, G->device, dev);
-    if ((J.op != SLIM_OP_TR && J.op != SLIM_OP_ES) || J.pad != 0)
+    if (!op_valid(J.op) || J.pad != 0)
       return fail(SLIM_EINVAL, "jobs[%u]: bad op %d", g, J.op);
     if (check_p(J.p)) return SLIM_EINVAL;
     num_cu = G->num_cu;

@@ -24,7 +24,7 @@ struct GDesc {
   uint64_t eb, ne;         // union CSR entries [eb, eb + ne)
   uint64_t thr;            // triangle selected / edge deleted iff Philox word 0 < thr
   uint32_t k0, k1;         // Philox key (seed)
-  uint32_t op;             // SLIM_OP_TR or SLIM_OP_ES
+  uint32_t op;             // SLIM_OP_* code of the graph's job
   uint32_t pad;
   uint64_t cap;            // capacity of out_col in entries
   const int64_t* in_row;   // the graph's own CSR (gather source of a batch)
@@ -116,10 +116,20 @@ struct TriArgs {
   const GDesc* gd;
   const TileRec* recs;     // graph-aligned tiles of at most tri_tile_max() entries
   uint64_t ntiles;
+  uint32_t* tcount;        // Min-Count: triangles per DAG edge (NULL if unused)
+  uint32_t pass;           // 0: Min-Count counting pass, 1: selection and marks
 };
 uint64_t tri_tile_max();
-void triangles(const TriArgs& a, uint32_t* tile_ctr, int num_cu, int blocks_per_cu,
-               int chunk, hipStream_t s);
+// `general` selects the instantiation that also runs Triangle p-2-Reduction
+// and both Min-Count passes; the plain one runs p-1 only.
+void triangles(const TriArgs& a, bool general, uint32_t* tile_ctr, int num_cu,
+               int blocks_per_cu, int chunk, hipStream_t s);
+
+// Op codes that list triangles.
+__host__ __device__ inline bool op_lists_triangles(uint32_t op) {
+  return op == SLIM_OP_TR || op == SLIM_OP_TR2 || op == SLIM_OP_MCTR;
+}
+__host__ __device__ inline bool op_valid(int op) { return op >= SLIM_OP_TR && op <= SLIM_OP_MCTR; }
 
 // Scheduling knobs; never change results.
 struct Tuning {

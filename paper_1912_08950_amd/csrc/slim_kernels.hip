@@ -443,9 +443,10 @@ struct OrientScatterPolicy {
   __device__ uint32_t value(const Ctx&, uint64_t j) const { return rcol[j]; }
 };
 
-// Output of a compression job, per graph: a TR graph keeps (r,c) iff its
-// edge is not marked deleted; an ES graph keeps {a<b} (local ids) iff
-// Philox(a,b,0,1) word 0 >= thr.  Written values are local ids.
+// Output of a compression job, per graph: a graph of a triangle operation
+// keeps (r,c) iff its edge is not marked deleted; an ES graph keeps {a<b}
+// (local ids) iff Philox(a,b,0,1) word 0 >= thr.  Written values are local
+// ids.
 struct OutPolicy {
   const uint32_t* col;
   const uint32_t* eid;
@@ -624,7 +625,7 @@ __global__ void k_stats(const GDesc* gd, uint32_t count, const uint64_t* tile0,
     if (!G.stats) continue;
     const uint64_t m = G.ne / 2;
     const uint64_t m_out = (tile_base[tile0[g + 1]] - tile_base[tile0[g]]) / 2;
-    const bool tr = G.op == SLIM_OP_TR && counters;
+    const bool tr = op_lists_triangles(G.op) && counters;
     slim_stats_t st;
     st.n = G.nv;
     st.m_in = m;

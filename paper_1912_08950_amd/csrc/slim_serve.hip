@@ -389,7 +389,7 @@ int slim_serve_create(const slim_serve_cfg_t* cfg, slim_server_t** out) {
 int slim_serve_submit(slim_server_t* S, const slim_job_t* job, uint64_t* ticket) {
   if (!S || !job || !ticket) return fail(SLIM_EINVAL, "NULL argument");
   const slim_job_t& J = *job;
-  if ((J.op != SLIM_OP_TR && J.op != SLIM_OP_ES) || J.pad || J.pad2)
+  if (!op_valid(J.op) || J.pad || J.pad2)
     return fail(SLIM_EINVAL, "job: bad op %d", J.op);
   if (check_p(J.p)) return SLIM_EINVAL;
   if (J.where != SLIM_HOST && J.where != SLIM_DEVICE)

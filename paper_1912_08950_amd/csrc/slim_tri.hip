@@ -18,6 +18,15 @@
 // in an LDS bitmap; (y,x) is a per-in-edge flag; (y,w) is an atomic OR into
 // the global bitmap over DAG positions.  All marks are idempotent ORs, so
 // the result does not depend on the order in which triangles are found.
+//
+// Variants (section 4.3), in the general instantiation of the kernel:
+// Triangle p-2-Reduction marks the two edges other than the drawn one;
+// Min-Count p-1-Reduction first runs a counting pass (every triangle adds 1
+// to each of its edges: LDS counters for (y,x) and (x,w), a global atomic
+// for (y,w)) and then marks, in each selected triangle, the edge of fewest
+// triangles (ties: the drawn index among the tied edges).
+#include <type_traits>
+
 #include "slim_internal.h"
 
 namespace slim {
@@ -62,6 +71,22 @@ struct TriSmem {
   uint64_t cmask[kTC];
   uint32_t bcast[4];
   uint64_t red[2][kTW];
+};
+
+// LDS of the general instantiation: per-edge triangle counts of the hashed
+// range and of the batch's in-edges (accumulated in the counting pass, loaded
+// for the Min-Count selection).
+struct TriX {
+  uint32_t xcnt[kHashCap];
+  uint32_t ie_cnt[kBatch];
+};
+
+struct TriSmemPlain {
+  TriSmem s;
+};
+struct TriSmemGeneral {
+  TriSmem s;
+  TriX x;
 };
 
 __device__ __forceinline__ uint32_t hbucket(uint32_t w, uint32_t xb) {
@@ -131,12 +156,14 @@ __device__ void tri_tile_rows(const int64_t* row_off, int64_t j0, uint32_t lo, u
 
 struct TriCtx {
   TriArgs a;
+  TriX* X;        // general instantiation only
   uint32_t cap;   // out-list entries hashed per pass (<= kHashCap)
   int64_t j0;
   uint32_t D0;    // first DAG position of the hashed range
   uint32_t hlen;  // number of hashed entries
   uint64_t thr;   // the tile's graph: selection threshold, Philox key, first vertex
   uint32_t k0, k1, vb;
+  uint32_t op;    // the tile's graph's operation
   uint64_t n_tri, n_sel;
 };
 
@@ -164,6 +191,9 @@ __device__ void tri_build_hash(TriCtx& C, TriSmem& S, uint32_t len, bool use_dpo
       b = (b + 1) & (kBuckets - 1);
     }
     S.xold[q] = C.a.order[w];
+    // counts exist only for Min-Count graphs: loaded for their selection
+    // pass, zeroed for their counting pass (other operations never read them)
+    if (C.X) C.X->xcnt[q] = C.a.pass == 1 && C.op == SLIM_OP_MCTR ? C.a.tcount[C.D0 + q] : 0u;
   }
   C.hlen = len;
   __syncthreads();
@@ -171,12 +201,19 @@ __device__ void tri_build_hash(TriCtx& C, TriSmem& S, uint32_t len, bool use_dpo
 
 __device__ void tri_flush_xbits(TriCtx& C, TriSmem& S) {
   __syncthreads();
-  const uint32_t nwords = (C.D0 % 32 + C.hlen + 31) / 32;
-  const uint32_t base = C.D0 / 32;
-  for (uint32_t i = threadIdx.x; i < nwords; i += kTB) {
-    const uint32_t v = S.xbits[i];
-    if (v)
-      __hip_atomic_fetch_or(C.a.del + base + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (C.X && C.a.pass == 0) {  // counting pass: add the (x,w) counts of the range
+    for (uint32_t q = threadIdx.x; q < C.hlen; q += kTB) {
+      const uint32_t v = C.X->xcnt[q];
+      if (v) atomicAdd(C.a.tcount + C.D0 + q, v);
+    }
+  } else {
+    const uint32_t nwords = (C.D0 % 32 + C.hlen + 31) / 32;
+    const uint32_t base = C.D0 / 32;
+    for (uint32_t i = threadIdx.x; i < nwords; i += kTB) {
+      const uint32_t v = S.xbits[i];
+      if (v)
+        __hip_atomic_fetch_or(C.a.del + base + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
   __syncthreads();
 }
@@ -197,12 +234,26 @@ __device__ void tri_forward_eids(TriCtx& C, TriSmem& S, uint32_t ia, uint32_t ib
   }
 }
 
+// Marks the edge of triangle (y,x,w) that does not contain vertex `excl`
+// (union ids: c = y, u0 = x, ow = w).
+__device__ __forceinline__ void tri_mark(uint32_t* del, TriSmem& S, uint32_t excl, uint32_t c,
+                                         uint32_t ow, uint32_t k, uint32_t qpos, uint32_t D0,
+                                         uint32_t p_yw) {
+  if (excl == ow) {  // edge {y,x}: flag of the in-edge
+    atomicOr(&S.ie_flag[k >> 5], 1u << (k & 31));
+  } else if (excl == c) {  // edge {x,w}: position qpos of the hashed range
+    const uint32_t bit = D0 % 32 + qpos;
+    atomicOr(&S.xbits[bit >> 5], 1u << (bit & 31));
+  } else {  // edge {y,w}: global bitmap (no return value: nothing waits on it)
+    bit_set(del, p_yw);
+  }
+}
+
 // Hash, select and mark the queued hits q[head .. head + cnt) (cnt <= 64);
 // one lane per hit.  Returns 1 in lanes whose triangle was selected.
-__device__ __forceinline__ uint32_t tri_drain(uint32_t* del, uint64_t thr, uint32_t k0,
-                                                        uint32_t k1, uint32_t vb, TriSmem* Sp,
-                                                        const uint2* q, uint32_t head,
-                                                        uint32_t cnt, uint32_t D0) {
+template <bool kGeneral>
+__device__ __forceinline__ uint32_t tri_drain(const TriCtx& C, TriSmem* Sp, const uint2* q,
+                                              uint32_t head, uint32_t cnt) {
   TriSmem& S = *Sp;
   const uint32_t lane = lane_id();
   uint32_t sel = 0;
@@ -213,21 +264,43 @@ __device__ __forceinline__ uint32_t tri_drain(uint32_t* del, uint64_t thr, uint3
     const uint32_t p_yw = ie.x + (rec.x - S.ie_pre[k]);
     const uint32_t ow = S.xold[qpos];
     const uint32_t c = ie.z, u0 = ie.w;
+    if (kGeneral && C.a.pass == 0) {  // counting pass: one more triangle on each edge
+      atomicAdd(&C.X->ie_cnt[k], 1u);
+      atomicAdd(&C.X->xcnt[qpos], 1u);
+      atomicAdd(C.a.tcount + p_yw, 1u);
+      return 0;
+    }
     uint32_t t0 = c, t1 = u0, t2 = ow;
     sort3(t0, t1, t2);  // union ids of one graph: the order of its local ids
     uint32_t w0, w1;
-    philox_w01(t0 - vb, t1 - vb, t2 - vb, 0u, k0, k1, w0, w1);
-    if ((uint64_t)w0 < thr) {
+    philox_w01(t0 - C.vb, t1 - C.vb, t2 - C.vb, 0u, C.k0, C.k1, w0, w1);
+    if ((uint64_t)w0 < C.thr) {
       sel = 1;
-      const uint32_t kk = __umulhi(w1, 3u);  // 0:{t0,t1} 1:{t0,t2} 2:{t1,t2}
-      const uint32_t excl = kk == 0 ? t2 : (kk == 1 ? t1 : t0);
-      if (excl == ow) {  // edge {y,x}: flag of the in-edge
-        atomicOr(&S.ie_flag[k >> 5], 1u << (k & 31));
-      } else if (excl == c) {  // edge {x,w}: position qpos of the hashed range
-        const uint32_t bit = D0 % 32 + qpos;
-        atomicOr(&S.xbits[bit >> 5], 1u << (bit & 31));
-      } else {  // edge {y,w}: global bitmap (no return value: nothing waits on it)
-        bit_set(del, p_yw);
+      // edge e of ({t0,t1}, {t0,t2}, {t1,t2}) is the one without excl[e]
+      const uint32_t excl[3] = {t2, t1, t0};
+      if (!kGeneral) {
+        tri_mark(C.a.del, S, excl[__umulhi(w1, 3u)], c, ow, k, qpos, C.D0, p_yw);
+      } else if (C.op == SLIM_OP_MCTR) {
+        uint32_t t[3];
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+          t[e] = excl[e] == ow ? C.X->ie_cnt[k]
+                               : (excl[e] == c ? C.X->xcnt[qpos] : C.a.tcount[p_yw]);
+        const uint32_t tmin = min(t[0], min(t[1], t[2]));
+        const uint32_t nt = (t[0] == tmin) + (t[1] == tmin) + (t[2] == tmin);
+        uint32_t pick = __umulhi(w1, nt), e = 0;
+        for (; e < 3; ++e) {
+          if (t[e] != tmin) continue;
+          if (pick == 0) break;
+          --pick;
+        }
+        tri_mark(C.a.del, S, excl[e], c, ow, k, qpos, C.D0, p_yw);
+      } else {
+        const uint32_t kk = __umulhi(w1, 3u);
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+          if ((C.op == SLIM_OP_TR2) ? (uint32_t)e != kk : (uint32_t)e == kk)
+            tri_mark(C.a.del, S, excl[e], c, ow, k, qpos, C.D0, p_yw);
       }
     }
   }
@@ -235,6 +308,7 @@ __device__ __forceinline__ uint32_t tri_drain(uint32_t* del, uint64_t thr, uint3
 }
 
 // Process the in-edges bw[b0, b1) of the tile against the current hash.
+template <bool kGeneral>
 __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool all_rows) {
   const int tid = threadIdx.x;
   const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -266,6 +340,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     xtag = all_rows ? (fs - C.D0) : 0u;
     S.ie[tid] = make_uint4(beg, x, c, r);
     S.ie_e[tid] = e;
+    if (kGeneral) C.X->ie_cnt[tid] = C.a.pass == 1 && C.op == SLIM_OP_MCTR ? C.a.tcount[e] : 0u;
     C.a.eid[j] = e;
     bmp = beg;
   }
@@ -381,7 +456,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
         qcnt += __popcll(bal);
         if (qcnt >= (uint32_t)kWave) {
           wave_sync();
-          C.n_sel += tri_drain(C.a.del, C.thr, C.k0, C.k1, C.vb, &S, q, qhead, kWave, C.D0);
+          C.n_sel += tri_drain<kGeneral>(C, &S, q, qhead, kWave);
           C.n_tri += 1;
           qhead = (qhead + kWave) % kQ;
           qcnt -= kWave;
@@ -391,13 +466,16 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
   }
   if (qcnt) {
     wave_sync();
-    C.n_sel += tri_drain(C.a.del, C.thr, C.k0, C.k1, C.vb, &S, q, qhead, qcnt, C.D0);
+    C.n_sel += tri_drain<kGeneral>(C, &S, q, qhead, qcnt);
     C.n_tri += lane < qcnt ? 1 : 0;
   }
   __syncthreads();
-  // ---- finish: (y,x) marks
-  if ((uint32_t)tid < nin && (S.ie_flag[tid >> 5] & (1u << (tid & 31))))
+  // ---- finish: (y,x) marks, or the (y,x) counts of the counting pass
+  if (kGeneral && C.a.pass == 0) {
+    if ((uint32_t)tid < nin && C.X->ie_cnt[tid]) atomicAdd(C.a.tcount + S.ie_e[tid], C.X->ie_cnt[tid]);
+  } else if ((uint32_t)tid < nin && (S.ie_flag[tid >> 5] & (1u << (tid & 31)))) {
     bit_set(C.a.del, S.ie_e[tid]);
+  }
   __syncthreads();
 }
 
@@ -427,12 +505,19 @@ __device__ void tri_flush_counts(TriCtx& C, TriSmem& S, uint32_t g) {
 // Persistent blocks take tiles in increasing order from a counter, so the
 // graph of a block's tiles never decreases: counts are flushed when it
 // changes and at the end.
+template <bool kGeneral>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k_triangles(
     TriArgs a, uint32_t* tile_ctr, uint32_t cap) {
-  __shared__ TriSmem S;
+  __shared__ std::conditional_t<kGeneral, TriSmemGeneral, TriSmemPlain> SS;
+  TriSmem& S = SS.s;
   TriCtx C;
   C.a = a;
+  if constexpr (kGeneral)
+    C.X = &SS.x;
+  else
+    C.X = nullptr;
   C.cap = cap;
+  C.op = 0;
   C.n_tri = 0;
   C.n_sel = 0;
   C.thr = 0;
@@ -449,14 +534,20 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (t >= ntiles) break;
     const TileRec R = a.recs[t];
     if (R.span == 0) continue;  // a graph without edges
+    const uint32_t gop = a.gd[R.g].op;
+    // tiles of edge-sampling graphs have no triangle work; the counting pass
+    // only visits Min-Count graphs
+    if (gop == SLIM_OP_ES || (kGeneral && a.pass == 0 && gop != SLIM_OP_MCTR)) continue;
     if (R.g != gcur) {
-      if (gcur != 0xffffffffu) tri_flush_counts(C, S, gcur);
+      // the counting pass reports no triangle or selection counts
+      if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0)) tri_flush_counts(C, S, gcur);
       gcur = R.g;
       const GDesc& G = a.gd[gcur];
       C.thr = G.thr;
       C.k0 = G.k0;
       C.k1 = G.k1;
       C.vb = (uint32_t)G.vb;
+      C.op = G.op;
     }
     const int64_t j0 = R.j0;
     const uint32_t span = R.span;
@@ -597,24 +688,29 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
       tri_build_hash(C, S, plen, all_rows);
       tri_forward_eids(C, S, pfa, pfb, all_rows);
       for (uint32_t b0 = pb0; b0 < pb1; b0 += kBatch)
-        tri_batch(C, S, b0, b0 + kBatch < pb1 ? b0 + kBatch : pb1, all_rows);
+        tri_batch<kGeneral>(C, S, b0, b0 + kBatch < pb1 ? b0 + kBatch : pb1, all_rows);
       tri_flush_xbits(C, S);
     }
   }
-  if (gcur != 0xffffffffu) tri_flush_counts(C, S, gcur);
+  if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0)) tri_flush_counts(C, S, gcur);
 }
 
 uint64_t tri_tile_max() { return kTT; }
 
-void triangles(const TriArgs& a, uint32_t* tile_ctr, int num_cu, int blocks_per_cu, int chunk,
-               hipStream_t s) {
+void triangles(const TriArgs& a, bool general, uint32_t* tile_ctr, int num_cu,
+               int blocks_per_cu, int chunk, hipStream_t s) {
   uint64_t blocks = (uint64_t)num_cu * blocks_per_cu;
   if (blocks > a.ntiles) blocks = a.ntiles;
   if (blocks < 1) blocks = 1;
   fill_u32(tile_ctr, 1, 0, s);
   uint32_t cap = (uint32_t)chunk;
   if (cap > (uint32_t)kHashCap) cap = kHashCap;
-  hipLaunchKernelGGL(k_triangles, dim3((unsigned)blocks), dim3(kTB), 0, s, a, tile_ctr, cap);
+  if (general)
+    hipLaunchKernelGGL(k_triangles<true>, dim3((unsigned)blocks), dim3(kTB), 0, s, a, tile_ctr,
+                       cap);
+  else
+    hipLaunchKernelGGL(k_triangles<false>, dim3((unsigned)blocks), dim3(kTB), 0, s, a, tile_ctr,
+                       cap);
 }
 
 }  // namespace slim

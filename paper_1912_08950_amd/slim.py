@@ -20,13 +20,13 @@ LIB_PATH = os.environ.get("SLIM_LIBRARY") or os.path.join(_HERE, "libslim.so")
 
 OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, EAGAIN = 0, -1, -2, -3, -4, -5
 VALIDATE = 1
-OP_TR, OP_ES = 1, 2
+OP_TR, OP_ES, OP_TR2, OP_MCTR = 1, 2, 3, 4
 STAT_KEYS = ("n", "m_in", "triangles", "selected", "deleted", "m_out")
 
 # Exported symbols of libslim.so, in include/slim.h order.
 SYMBOLS = ("slim_last_error", "slim_strerror", "slim_version", "slim_load_csr",
            "slim_graph_free", "slim_workspace_size", "slim_triangle_reduce", "slim_edge_sample",
-           "slim_batch_create", "slim_batch_workspace_size", "slim_batch_run", "slim_batch_set",
+           "slim_compress", "slim_batch_create", "slim_batch_workspace_size", "slim_batch_run", "slim_batch_set",
            "slim_batch_get", "slim_batch_tune", "slim_batch_free",
            "slim_serve_create", "slim_serve_submit", "slim_serve_poll", "slim_serve_wait",
            "slim_serve_next", "slim_serve_cancel", "slim_serve_copy", "slim_result_release", "slim_serve_stats",
@@ -112,6 +112,8 @@ def _bind(path: str = LIB_PATH):
     for fn in (lib.slim_triangle_reduce, lib.slim_edge_sample):
         fn.restype = i32
         fn.argtypes = [vp, dbl, u64, vp, u64, vp, vp, vp, vp]
+    lib.slim_compress.restype = i32
+    lib.slim_compress.argtypes = [vp, i32, dbl, u64, vp, u64, vp, vp, vp, vp]
     lib.slim_batch_create.restype = i32
     lib.slim_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(JobParams), u32,
                                       ctypes.POINTER(vp)]
@@ -294,6 +296,18 @@ def triangle_reduce(g: Graph, p: float, seed: int, bufs: Buffers | None = None, 
 def edge_sample(g: Graph, p: float, seed: int, bufs: Buffers | None = None, stream=None):
     """Enqueue uniform edge sampling (p = deletion probability)."""
     return _run(_lib.slim_edge_sample, g, p, seed, bufs, stream)
+
+
+def compress(g: Graph, op: int, p: float, seed: int, bufs: Buffers | None = None, stream=None):
+    """Enqueue any operation by op code (OP_TR, OP_ES, OP_TR2, OP_MCTR)."""
+    if bufs is None:
+        bufs = Buffers(g, op)
+    with torch.cuda.device(g.device):
+        rc = _lib.slim_compress(g._h, int(op), float(p), int(seed) & (2**64 - 1), bufs.ws.data_ptr(),
+                                bufs.ws_bytes, bufs.out_row_off.data_ptr(), bufs.out_col.data_ptr(),
+                                bufs.stats.data_ptr(), _stream_handle(stream, g.device))
+    _check(rc)
+    return bufs
 
 
 def result_numpy(bufs: Buffers):

@@ -260,3 +260,59 @@ def test_rmat24_tr_full(slim, rmat24):
 
 def test_rmat24_es_full(slim, rmat24):
     _check_digest(slim, rmat24, "rmat24_es_p0.5")
+
+
+
+# ------------------------------- Triangle p-2 and Min-Count p-1 variants
+
+VARIANTS = {"tr2": 2, "mctr": 3}
+
+
+def gpu_run_op(slim, g, name, p, seed, validate=False):
+    op = {"tr2": slim.OP_TR2, "mctr": slim.OP_MCTR}[name]
+    dg = slim.Graph.from_csr(g, validate=validate)
+    return slim.result_numpy(slim.compress(dg, op, p, seed))
+
+
+def oracle_run_x(g, name, p, seed):
+    ro, col, st = O.triangle_reduce_x(g, p, seed, VARIANTS[name])
+    return ro, col, {"n": st["n"], "m_in": st["m_in"], "triangles": st["T"],
+                     "selected": st["selected"], "deleted": st["deleted"], "m_out": st["m_out"]}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_small_graphs_variants(slim, name, variant):
+    g = SMALL[name]()
+    for p, seed in ((0.5, 1), (0.0, 2), (1.0, 3), (0.2, 4), (0.8, 5)):
+        assert_same(gpu_run_op(slim, g, variant, p, seed), oracle_run_x(g, variant, p, seed),
+                    f"{name} {variant} p={p} seed={seed}")
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_variants_cfg1_and_rmat(slim, variant):
+    g = gg.er(2000, 16.0, 1)
+    for seed in range(1, 9):
+        assert_same(gpu_run_op(slim, g, variant, 0.5, seed), oracle_run_x(g, variant, 0.5, seed))
+    for scale in (14, 16):
+        g = gg.rmat(scale, 16, 1)
+        for p in (0.2, 0.8):
+            assert_same(gpu_run_op(slim, g, variant, p, 1), oracle_run_x(g, variant, p, 1),
+                        f"s{scale} {variant} p={p}")
+
+
+@pytest.mark.parametrize("knobs", [{"tri_chunk": 32}, {"tri_tile": 256, "tri_blocks_per_cu": 1},
+                                   {"tri_chunk": 512, "tri_blocks_per_cu": 3}])
+def test_variants_schedule_independence(slim, knobs):
+    graphs = [gg.rmat(13, 16, 2), bipartite_plus_matching(3, 300), wheel(5000)]
+    want = {(g.name, v): oracle_run_x(g, v, 0.6, 4) for g in graphs for v in VARIANTS}
+    old = {k: slim.tune_get(k) for k in knobs}
+    try:
+        for k, v in knobs.items():
+            slim.tune_set(k, v)
+        for g in graphs:
+            for v in VARIANTS:
+                assert_same(gpu_run_op(slim, g, v, 0.6, 4), want[(g.name, v)], f"{g.name} {v}")
+    finally:
+        for k, v in old.items():
+            slim.tune_set(k, v)
