@@ -54,6 +54,8 @@ def _load():
         fn.restype = ctypes.c_int
     lib.orc_triangle_reduce_x.argtypes = [u64, vp, vp, dbl, u64, ctypes.c_int, vp, vp, vp]
     lib.orc_triangle_reduce_x.restype = ctypes.c_int
+    lib.orc_spectral_sparsify.argtypes = [u64, vp, vp, dbl, u64, vp, vp, vp, vp]
+    lib.orc_spectral_sparsify.restype = ctypes.c_int
     lib.orc_tr_rows.argtypes = [u64, vp, vp, dbl, u64, vp, u64, vp, vp]
     lib.orc_tr_rows.restype = ctypes.c_int
     lib.orc_edge_triangle_counts.argtypes = [u64, vp, vp, vp]
@@ -133,6 +135,26 @@ def triangle_reduce_x(g, p: float, seed: int, variant: int):
         return lib.orc_triangle_reduce_x(n, ro, col, p_, seed_, int(variant), oro, ocol, st)
 
     return _run(fn, g, p, seed)
+
+
+def spectral_sparsify(g, upsilon: float, seed: int):
+    """Spectral sparsification (keep {u,v} with p_uv = min(1, upsilon /
+    min(d_u, d_v)), weight 1/p_uv): (row_off, col, weights float32, stats)."""
+    lib = _load()
+    ro, col = _arrays(g)
+    out_ro = np.zeros(g.n + 1, dtype=np.int64)
+    out_col = np.zeros(max(g.nnz, 1), dtype=np.uint32)
+    out_w = np.zeros(max(g.nnz, 1), dtype=np.float32)
+    stats = np.zeros(6, dtype=np.uint64)
+    rc = lib.orc_spectral_sparsify(g.n, ro.ctypes.data, col.ctypes.data, float(upsilon),
+                                   int(seed) & (2**64 - 1), out_ro.ctypes.data, out_col.ctypes.data,
+                                   out_w.ctypes.data, stats.ctypes.data)
+    if rc == -1:
+        raise ValueError(f"upsilon must be >= 0, got {upsilon!r}")
+    if rc != 0:
+        raise RuntimeError(f"oracle failed rc={rc}")
+    k = int(out_ro[-1])
+    return out_ro, out_col[:k].copy(), out_w[:k].copy(), dict(zip(STAT_KEYS, (int(x) for x in stats)))
 
 
 def edge_sample(g, p: float, seed: int):

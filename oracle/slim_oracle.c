@@ -36,6 +36,10 @@
  *       the input graph that contain e; a selected triangle removes its
  *       edge of smallest t_e, ties broken uniformly by word x1 among the
  *       tied edges in the order of R4.
+ *   R7  Spectral sparsification (section 4.2.1, kernel spectral_sparsify):
+ *       the kernel keeps an edge when rand <= p_uv, so p_uv is the keep
+ *       probability; upsilon is passed in directly (the paper suggests
+ *       p log n or p m/n); the counter domain of the edge draw is (u,v,0,2).
  *   R4  The random source `SG.rand` is unspecified in the paper; here it is
  *       Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
  *       key = (seed mod 2^32, seed div 2^32).  For the triangle {a<b<c}
@@ -463,6 +467,56 @@ int orc_edge_sample(uint64_t n, const int64_t* row_off, const uint32_t* col, dou
         if ((uint64_t)c > r) deleted++;
       } else {
         out_col[k++] = c;
+      }
+    }
+    out_row_off[r + 1] = k;
+  }
+  stats[0] = n;
+  stats[1] = nnz / 2;
+  stats[2] = 0;
+  stats[3] = 0;
+  stats[4] = deleted;
+  stats[5] = nnz / 2 - deleted;
+  return 0;
+}
+
+/* ------------------------------- spectral sparsification (4.2.1)
+ * Kernel spectral_sparsify: the edge {u<v} stays with probability
+ * p_uv = min(1, upsilon / min(d_u, d_v)) (degrees of the input graph) and a
+ * kept edge gets weight 1/p_uv.  Decided once per edge from counter
+ * (u,v,0,2): kept iff word 0 < floor(p_uv * 2^32) (2^32 when p_uv = 1), with
+ * p_uv computed in double precision (R7).  out_w (float, may be NULL) gets the
+ * weight of every output entry, (float)(1.0 / p_uv).  stats as
+ * orc_edge_sample.  upsilon must be >= 0 (NaN -> -1).
+ */
+int orc_spectral_sparsify(uint64_t n, const int64_t* row_off, const uint32_t* col, double upsilon,
+                          uint64_t seed, int64_t* out_row_off, uint32_t* out_col, float* out_w,
+                          uint64_t* stats) {
+  if (!(upsilon >= 0.0)) return -1;
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint64_t nnz = (uint64_t)row_off[n];
+  int64_t k = 0;
+  uint64_t deleted = 0;
+  out_row_off[0] = 0;
+  for (uint64_t r = 0; r < n; ++r) {
+    for (int64_t j = row_off[r]; j < row_off[r + 1]; ++j) {
+      uint32_t c = col[j];
+      uint32_t a = (uint64_t)c < r ? c : (uint32_t)r;
+      uint32_t b = (uint64_t)c < r ? (uint32_t)r : c;
+      int64_t da = row_off[a + 1] - row_off[a], db = row_off[b + 1] - row_off[b];
+      double dmin = (double)(da < db ? da : db);
+      double pe = upsilon / dmin;
+      if (pe > 1.0) pe = 1.0;
+      uint64_t thr;
+      orc_threshold(pe, &thr);
+      uint32_t ctr[4] = {a, b, 0u, 2u};
+      uint32_t x[4];
+      orc_philox4x32_10(ctr, key, x);
+      if ((uint64_t)x[0] < thr) {
+        if (out_w) out_w[k] = (float)(1.0 / pe);
+        out_col[k++] = c;
+      } else if ((uint64_t)c > r) {
+        deleted++;
       }
     }
     out_row_off[r + 1] = k;

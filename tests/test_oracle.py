@@ -468,3 +468,89 @@ def test_min_count_deletes_only_minimal_edges(cfg1):
         ok |= {e for e in es if cnt[e] == tmin}
     assert deleted and deleted <= ok
     assert st["deleted"] <= st["selected"] == st["T"]
+
+
+# ------------------------------------------------- spectral sparsification
+
+def _pe(g, a, b, ups):
+    da = g.row_off[a + 1] - g.row_off[a]
+    db = g.row_off[b + 1] - g.row_off[b]
+    return min(1.0, ups / float(min(da, db)))
+
+
+def test_spectral_keeps_everything_when_upsilon_reaches_degrees(cfg1):
+    """upsilon >= every degree: p_uv = 1 for all edges, weights exactly 1."""
+    dmax = int(np.diff(cfg1.row_off).max())
+    ro, col, w, st = O.spectral_sparsify(cfg1, float(dmax), 3)
+    assert np.array_equal(ro, cfg1.row_off) and np.array_equal(col, cfg1.col)
+    assert np.all(w == 1.0) and st["deleted"] == 0
+
+
+def test_spectral_zero_upsilon_deletes_everything(cfg1):
+    ro, col, w, st = O.spectral_sparsify(cfg1, 0.0, 3)
+    assert ro[-1] == 0 and st["m_out"] == 0 and st["deleted"] == cfg1.m
+
+
+def test_spectral_regular_graph_is_uniform_sampling():
+    """On a cycle (all degrees 2) with upsilon = 1, p_uv = 1/2 for every edge:
+    deletions ~ Bin(m, 1/2), every kept weight is exactly 2."""
+    g = gg.cycle(4000)
+    zs = []
+    for s in range(20):
+        ro, col, w, st = O.spectral_sparsify(g, 1.0, s)
+        assert np.all(w == 2.0)
+        zs.append((st["deleted"] - 2000) / math.sqrt(4000 * 0.25))
+    assert abs(np.sum(zs) / math.sqrt(len(zs))) < 4.0
+
+
+def test_spectral_star_keeps_leaf_edges():
+    """Star: every edge has a degree-1 end, so p_uv = min(1, upsilon) = 1 for
+    upsilon >= 1 -- the scheme never disconnects a leaf."""
+    g = gg.star(500)
+    ro, col, w, st = O.spectral_sparsify(g, 1.0, 9)
+    assert st["deleted"] == 0 and np.all(w == 1.0)
+
+
+def test_spectral_decisions_match_definition(cfg1):
+    """Edge by edge on a small graph: kept iff Philox(u,v,0,2) word 0 <
+    floor(p_uv 2^32), weight (float)(1/p_uv), both copies alike."""
+    g = gg.er(300, 12.0, 4)
+    ups = 4.5
+    ro, col, w, st = O.spectral_sparsify(g, ups, 77)
+    kept = {}
+    for r in range(g.n):
+        for k in range(ro[r], ro[r + 1]):
+            kept[(r, int(col[k]))] = float(w[k])
+    key = (77, 0)
+    for a, b in undirected(g.row_off, g.col):
+        pe = _pe(g, a, b, ups)
+        thr = O.threshold(pe)
+        x = O.philox4x32_10((a, b, 0, 2), key)
+        stays = x[0] < thr
+        assert ((a, b) in kept) == stays and ((b, a) in kept) == stays
+        if stays:
+            assert kept[(a, b)] == float(np.float32(1.0 / pe)) == kept[(b, a)]
+
+
+def test_spectral_weighted_edge_count_is_unbiased():
+    """E[sum of kept weights] = m (each edge contributes p_uv * 1/p_uv), and
+    E[edges kept] = sum p_uv."""
+    g = gg.rmat(11, 8, 2)
+    ups = 3.0
+    pes = np.array([_pe(g, a, b, ups) for a, b in undirected(g.row_off, g.col)])
+    wsum, kept = [], []
+    for s in range(40):
+        ro, col, w, st = O.spectral_sparsify(g, ups, s)
+        wsum.append(w.sum(dtype=np.float64) / 2)
+        kept.append(st["m_out"])
+    var_w = float(np.sum((1 - pes) / pes))
+    var_k = float(np.sum(pes * (1 - pes)))
+    assert abs(np.mean(wsum) - g.m) < 5 * math.sqrt(var_w / 40) + 1
+    assert abs(np.mean(kept) - pes.sum()) < 5 * math.sqrt(var_k / 40) + 1
+
+
+def test_spectral_rejects_bad_upsilon(cfg1):
+    with pytest.raises(ValueError):
+        O.spectral_sparsify(cfg1, float("nan"), 1)
+    with pytest.raises(ValueError):
+        O.spectral_sparsify(cfg1, -1.0, 1)
