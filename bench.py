@@ -390,6 +390,26 @@ def main():
                      "scan_bytes_per_s": 4 * work["sum_out_pairs"] / (tri_ms * 1e-3)},
         "step_algorithmic_gbs": step_bytes(g, work, stats["m_out"]) / (ms_per_step * 1e-3) / 1e9,
     }
+    # the other triangle operations on the same graph (Triangle p-2-Reduction,
+    # Min-Count p-1-Reduction: counting pass + selection pass)
+    variants = {}
+    for name, op in (("tr2", slim.OP_TR2), ("mctr", slim.OP_MCTR)):
+        vb = slim.Buffers(dg, op)
+        slim.compress(dg, op, args.p, args.seed, vb)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        reps = 3
+        for _ in range(reps):
+            slim.compress(dg, op, args.p, args.seed, vb)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        vst = dict(zip(slim.STAT_KEYS, (int(x) for x in vb.stats.cpu().numpy())))
+        variants[name] = {"ms": ms, "edges_per_s": g.m / (ms * 1e-3), "stats": vst}
+        log(f"{name}: {ms:.2f} ms {vst}")
+        del vb
+    result["variants"] = variants
     del bufs, es_bufs, dg
     torch.cuda.empty_cache()
     if args.batch_count > 0:

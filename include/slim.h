@@ -83,6 +83,7 @@ SLIM_API void slim_graph_free(slim_graph_t* g);
 #define SLIM_OP_ES 2   /* uniform edge sampling */
 #define SLIM_OP_TR2 3  /* Triangle p-2-Reduction */
 #define SLIM_OP_MCTR 4 /* Min-Count Triangle p-1-Reduction */
+#define SLIM_OP_SPECTRAL 5 /* spectral sparsification (p carries upsilon) */
 
 /* Device workspace (bytes) that `op` needs on graph `g`. */
 SLIM_API int slim_workspace_size(const slim_graph_t* g, int op, uint64_t* bytes);
@@ -149,10 +150,30 @@ SLIM_API int slim_edge_sample(const slim_graph_t* g, double p, uint64_t seed, vo
  *                 triangle loses its edge of smallest t_e; among tied edges
  *                 (in the order {a,b}, {a,c}, {b,c}) the one at index
  *                 floor(word1 * ties / 2^32).
+ *   SLIM_OP_SPECTRAL  as slim_spectral_sparsify with upsilon = p (any value
+ *                 >= 0) and no weights.
  */
 SLIM_API int slim_compress(const slim_graph_t* g, int op, double p, uint64_t seed, void* d_ws,
                            uint64_t ws_bytes, int64_t* d_out_row_off, uint32_t* d_out_col,
                            slim_stats_t* d_stats, void* stream);
+
+/*
+ * Spectral sparsification (section 4.2.1; kernel spectral_sparsify): the
+ * edge {a<b} stays with probability p_ab = min(1, upsilon / min(d_a, d_b))
+ * (degrees of the input graph; the paper suggests upsilon = p log n or
+ * p m/n) and a kept edge weighs 1/p_ab.  Decided once per edge from
+ * Philox4x32-10 with counter (a,b,0,2): kept iff word 0 < floor(p_ab * 2^32)
+ * (2^32 when p_ab = 1), p_ab computed in IEEE double precision.
+ *   upsilon         >= 0 (NaN or negative -> SLIM_EINVAL).
+ *   d_out_weight    optional float32[nnz] capacity: weight (float)(1/p_ab)
+ *                   of every output entry, aligned with d_out_col.
+ * Other arguments as slim_edge_sample (workspace:
+ * slim_workspace_size(g, SLIM_OP_SPECTRAL)).
+ */
+SLIM_API int slim_spectral_sparsify(const slim_graph_t* g, double upsilon, uint64_t seed,
+                                    void* d_ws, uint64_t ws_bytes, int64_t* d_out_row_off,
+                                    uint32_t* d_out_col, float* d_out_weight, slim_stats_t* d_stats,
+                                    void* stream);
 
 /* ------------------------------------------------------------ batches
  * Many graphs in one launch sequence: the graphs are gathered into one
@@ -182,6 +203,7 @@ typedef struct slim_out {
   int64_t* row_off;    /* device int64[n+1] */
   uint32_t* col;       /* device uint32[nnz] capacity (may be NULL if nnz = 0) */
   slim_stats_t* stats; /* optional device stats */
+  float* weight;       /* optional device float32[nnz]: SLIM_OP_SPECTRAL weights */
 } slim_out_t;
 
 typedef struct slim_batch slim_batch_t; /* opaque, library-owned */

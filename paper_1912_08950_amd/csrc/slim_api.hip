@@ -80,6 +80,14 @@ int check_p(double p) {
   return SLIM_OK;
 }
 
+int check_param(int op, double p) {
+  if (op == SLIM_OP_SPECTRAL) {
+    if (!(p >= 0.0)) return fail(SLIM_EINVAL, "upsilon must be >= 0, got %g", p);
+    return SLIM_OK;
+  }
+  return check_p(p);
+}
+
 // 8-bit radix passes that order degrees up to maxdeg.
 int radix_passes(uint64_t maxdeg) {
   int bits = 0;
@@ -367,10 +375,10 @@ using namespace slim;
 
 namespace {
 
-int check_call(const slim_graph* g, double p, void* ws, uint64_t ws_bytes, uint64_t need,
+int check_call(const slim_graph* g, int op, double p, void* ws, uint64_t ws_bytes, uint64_t need,
                int64_t* out_ro, uint32_t* out_col) {
   if (!g) return fail(SLIM_EINVAL, "graph handle is NULL");
-  if (check_p(p)) return SLIM_EINVAL;
+  if (check_param(op, p)) return SLIM_EINVAL;
   if (!out_ro) return fail(SLIM_EINVAL, "d_out_row_off is NULL");
   if (g->nnz && !out_col) return fail(SLIM_EINVAL, "d_out_col is NULL");
   if (ws_bytes < need)
@@ -389,19 +397,21 @@ struct SingleHdr {
   uint64_t t0t[2];
   uint64_t t0u[2];
 };
-static_assert(sizeof(SingleHdr) <= 256, "one put_bytes launch");
-static_assert(sizeof(GDesc) == 104, "descriptor size");
+static_assert(sizeof(SingleHdr) <= 512, "one put_bytes launch");
+static_assert(sizeof(GDesc) == 120, "descriptor size");
 
 int single_op(int op, const slim_graph* g, double p, uint64_t seed, void* ws, uint64_t ws_bytes,
-              int64_t* out_ro, uint32_t* out_col, slim_stats_t* stats, hipStream_t s) {
+              int64_t* out_ro, uint32_t* out_col, float* out_w, slim_stats_t* stats,
+              hipStream_t s) {
   if (!op_valid(op)) return fail(SLIM_EINVAL, "unknown op %d", op);
   const bool tr = op_lists_triangles((uint32_t)op);
-  const char* what = op == SLIM_OP_TR ? "slim_triangle_reduce"
-                     : op == SLIM_OP_ES ? "slim_edge_sample"
-                                        : "slim_compress";
+  const char* what = op == SLIM_OP_TR         ? "slim_triangle_reduce"
+                     : op == SLIM_OP_ES       ? "slim_edge_sample"
+                     : op == SLIM_OP_SPECTRAL ? "slim_spectral_sparsify"
+                                              : "slim_compress";
   const SetShape S = g ? single_shape(g->n, g->nnz, op) : SetShape{};
   const uint64_t need = g && g->nnz ? set_layout(S).total : 0;
-  if (int rc = check_call(g, p, ws, ws_bytes, need, out_ro, out_col)) return rc;
+  if (int rc = check_call(g, op, p, ws, ws_bytes, need, out_ro, out_col)) return rc;
   (void)hipGetLastError();
   prof_reset();
   if (g->nnz == 0) {
@@ -426,7 +436,8 @@ int single_op(int op, const slim_graph* g, double p, uint64_t seed, void* ws, ui
   d.nv = g->n;
   d.eb = 0;
   d.ne = g->nnz;
-  d.thr = threshold(p);
+  d.thr = op == SLIM_OP_SPECTRAL ? 0 : threshold(p);
+  d.ups = op == SLIM_OP_SPECTRAL ? p : 0.0;
   d.k0 = (uint32_t)seed;
   d.k1 = (uint32_t)(seed >> 32);
   d.op = (uint32_t)op;
@@ -435,6 +446,7 @@ int single_op(int op, const slim_graph* g, double p, uint64_t seed, void* ws, ui
   d.in_col = g->col;
   d.out_row = out_ro;
   d.out_col = out_col;
+  d.out_w = out_w;
   d.stats = stats;
   h.gd[1] = union_desc(S, L, ws);
   h.t0c[0] = 0;
@@ -550,22 +562,31 @@ int slim_workspace_size(const slim_graph_t* g, int op, uint64_t* bytes) {
 int slim_triangle_reduce(const slim_graph_t* g, double p, uint64_t seed, void* d_ws,
                          uint64_t ws_bytes, int64_t* d_out_row_off, uint32_t* d_out_col,
                          slim_stats_t* d_stats, void* stream) {
-  return single_op(SLIM_OP_TR, g, p, seed, d_ws, ws_bytes, d_out_row_off, d_out_col, d_stats,
+  return single_op(SLIM_OP_TR, g, p, seed, d_ws, ws_bytes, d_out_row_off, d_out_col, nullptr,
+                   d_stats,
                    static_cast<hipStream_t>(stream));
 }
 
 int slim_compress(const slim_graph_t* g, int op, double p, uint64_t seed, void* d_ws,
                   uint64_t ws_bytes, int64_t* d_out_row_off, uint32_t* d_out_col,
                   slim_stats_t* d_stats, void* stream) {
-  return single_op(op, g, p, seed, d_ws, ws_bytes, d_out_row_off, d_out_col, d_stats,
+  return single_op(op, g, p, seed, d_ws, ws_bytes, d_out_row_off, d_out_col, nullptr, d_stats,
                    static_cast<hipStream_t>(stream));
 }
 
 int slim_edge_sample(const slim_graph_t* g, double p, uint64_t seed, void* d_ws,
                      uint64_t ws_bytes, int64_t* d_out_row_off, uint32_t* d_out_col,
                      slim_stats_t* d_stats, void* stream) {
-  return single_op(SLIM_OP_ES, g, p, seed, d_ws, ws_bytes, d_out_row_off, d_out_col, d_stats,
+  return single_op(SLIM_OP_ES, g, p, seed, d_ws, ws_bytes, d_out_row_off, d_out_col, nullptr,
+                   d_stats,
                    static_cast<hipStream_t>(stream));
+}
+
+int slim_spectral_sparsify(const slim_graph_t* g, double upsilon, uint64_t seed, void* d_ws,
+                           uint64_t ws_bytes, int64_t* d_out_row_off, uint32_t* d_out_col,
+                           float* d_out_weight, slim_stats_t* d_stats, void* stream) {
+  return single_op(SLIM_OP_SPECTRAL, g, upsilon, seed, d_ws, ws_bytes, d_out_row_off, d_out_col,
+                   d_out_weight, d_stats, static_cast<hipStream_t>(stream));
 }
 
 int slim_profile_enable(int on) {

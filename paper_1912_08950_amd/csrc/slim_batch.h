@@ -53,6 +53,9 @@ int hip_check(const char* what);
 const char* last_error();
 uint64_t threshold(double p);
 int check_p(double p);
+// p of an operation: a probability in [0,1], or upsilon >= 0 for spectral
+// sparsification.
+int check_param(int op, double p);
 int radix_passes(uint64_t maxdeg);
 uint64_t tiles_of(uint64_t ne, uint64_t tile);
 SetLayout set_layout(const SetShape& S);

@@ -135,6 +135,7 @@ void build_header(slim_batch* b, void* ws, const slim_out_t* outs) {
     b->plan.gd[g].out_row = outs[g].row_off;
     b->plan.gd[g].out_col = outs[g].col;
     b->plan.gd[g].stats = outs[g].stats;
+    b->plan.gd[g].out_w = outs[g].weight;
   }
   fill_header(b->plan, b->layout, b->knobs, ws, b->hdr);
 }
@@ -267,12 +268,13 @@ int slim_batch_create(const slim_graph_t* const* graphs, const slim_job_params_t
       return fail(SLIM_EINVAL, "graphs[%u] lives on device %d, not %d", g, G->device, dev);
     if (!op_valid(J.op) || J.pad != 0)
       return fail(SLIM_EINVAL, "jobs[%u]: bad op %d", g, J.op);
-    if (check_p(J.p)) return SLIM_EINVAL;
+    if (check_param(J.op, J.p)) return SLIM_EINVAL;
     num_cu = G->num_cu;
     GDesc& d = gs[g];
     d.nv = G->n;
     d.ne = G->nnz;
-    d.thr = threshold(J.p);
+    d.thr = J.op == SLIM_OP_SPECTRAL ? 0 : threshold(J.p);
+    d.ups = J.op == SLIM_OP_SPECTRAL ? J.p : 0.0;
     d.k0 = (uint32_t)J.seed;
     d.k1 = (uint32_t)(J.seed >> 32);
     d.op = (uint32_t)J.op;

@@ -23,6 +23,7 @@ struct GDesc {
   uint64_t vb, nv;         // union vertices [vb, vb + nv)
   uint64_t eb, ne;         // union CSR entries [eb, eb + ne)
   uint64_t thr;            // triangle selected / edge deleted iff Philox word 0 < thr
+  double ups;              // spectral sparsification parameter upsilon
   uint32_t k0, k1;         // Philox key (seed)
   uint32_t op;             // SLIM_OP_* code of the graph's job
   uint32_t pad;
@@ -31,6 +32,7 @@ struct GDesc {
   const uint32_t* in_col;
   void* out_row;           // row starts, nv + 1 (int64; uint32 for the DAG)
   uint32_t* out_col;       // columns, local ids
+  float* out_w;            // spectral sparsification: weight per output entry (optional)
   slim_stats_t* stats;     // optional
 };
 
@@ -58,7 +60,7 @@ void degree_rank(const int64_t* row_off, uint64_t n, int passes, uint32_t* ka, u
                  uint32_t* kb, uint32_t* vb, uint32_t* hist, uint64_t* hist_scan,
                  uint64_t* scan_tmp, uint32_t** order_out, uint32_t* rank, hipStream_t s);
 
-// Copies up to 256 bytes of host data (descriptors) to device memory by a
+// Copies up to 512 bytes of host data (descriptors) to device memory by a
 // kernel launch: no host-to-device copy, so it can sit in a captured graph.
 void put_bytes(void* dst, const void* src, uint32_t bytes, hipStream_t s);
 // Tile records of a set with `tile` entries per tile; tile0[g] is the first
@@ -129,7 +131,9 @@ void triangles(const TriArgs& a, bool general, uint32_t* tile_ctr, int num_cu,
 __host__ __device__ inline bool op_lists_triangles(uint32_t op) {
   return op == SLIM_OP_TR || op == SLIM_OP_TR2 || op == SLIM_OP_MCTR;
 }
-__host__ __device__ inline bool op_valid(int op) { return op >= SLIM_OP_TR && op <= SLIM_OP_MCTR; }
+__host__ __device__ inline bool op_valid(int op) {
+  return op >= SLIM_OP_TR && op <= SLIM_OP_SPECTRAL;
+}
 
 // Scheduling knobs; never change results.
 struct Tuning {

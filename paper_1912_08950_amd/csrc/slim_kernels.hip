@@ -255,11 +255,11 @@ void degree_rank(const int64_t* row_off, uint64_t n, int passes, uint32_t* ka, u
 }
 
 // --------------------------------------------------------- small writes
-// Copies up to 256 bytes of host data to device memory as a kernel argument,
+// Copies up to 512 bytes of host data to device memory as a kernel argument,
 // so that a call can set up its descriptors without a host-to-device copy
 // (and stays capturable in a HIP graph).
 struct Blob {
-  uint32_t w[64];
+  uint32_t w[128];
 };
 
 __global__ void k_put(uint32_t* dst, Blob b, uint32_t words) {
@@ -269,7 +269,7 @@ __global__ void k_put(uint32_t* dst, Blob b, uint32_t words) {
 void put_bytes(void* dst, const void* src, uint32_t bytes, hipStream_t s) {
   Blob b{};
   __builtin_memcpy(b.w, src, bytes);
-  hipLaunchKernelGGL(k_put, dim3(1), dim3(64), 0, s, static_cast<uint32_t*>(dst), b,
+  hipLaunchKernelGGL(k_put, dim3(1), dim3(128), 0, s, static_cast<uint32_t*>(dst), b,
                      (bytes + 3) / 4);
 }
 
@@ -419,6 +419,7 @@ __device__ __forceinline__ uint32_t tile_row_of(const TileRows& L, int i) {
 // counting pass gathers rank(c) once per entry and streams it to rcol; the
 // scatter pass and the triangle kernel read rcol instead of gathering.
 struct OrientCountPolicy {
+  static constexpr bool kWeights = false;
   const uint32_t* col;
   const uint32_t* rank;
   uint32_t* rcol;
@@ -434,6 +435,7 @@ struct OrientCountPolicy {
 };
 
 struct OrientScatterPolicy {
+  static constexpr bool kWeights = false;
   const uint32_t* rcol;
   const uint32_t* rank;
   struct Ctx {};
@@ -445,33 +447,57 @@ struct OrientScatterPolicy {
 
 // Output of a compression job, per graph: a graph of a triangle operation
 // keeps (r,c) iff its edge is not marked deleted; an ES graph keeps {a<b}
-// (local ids) iff Philox(a,b,0,1) word 0 >= thr.  Written values are local
-// ids.
+// (local ids) iff Philox(a,b,0,1) word 0 >= thr; a spectral sparsification
+// graph keeps {a<b} iff Philox(a,b,0,2) word 0 < floor(p_ab 2^32) with
+// p_ab = min(1, upsilon / min(d_a, d_b)) in double precision (section 4.2.1)
+// and weighs it 1/p_ab.  Written values are local ids.
 struct OutPolicy {
+  static constexpr bool kWeights = true;
   const uint32_t* col;
   const uint32_t* eid;
   const uint32_t* del;
+  const int64_t* row_off;
   uint64_t m;
   struct Ctx {
     uint64_t thr;
-    uint32_t vb, k0, k1, es;
+    double ups;
+    uint32_t vb, k0, k1, mode;  // mode: 0 triangle ops, 1 ES, 2 spectral
   };
   __device__ Ctx ctx(const GDesc& G) const {
-    return Ctx{G.thr, (uint32_t)G.vb, G.k0, G.k1, G.op == SLIM_OP_ES ? 1u : 0u};
+    return Ctx{G.thr, G.ups, (uint32_t)G.vb, G.k0, G.k1,
+               G.op == SLIM_OP_ES ? 1u : (G.op == SLIM_OP_SPECTRAL ? 2u : 0u)};
   }
-  __device__ bool needs_rows(const GDesc& G) const { return G.op == SLIM_OP_ES; }
+  __device__ bool needs_rows(const GDesc& G) const {
+    return G.op == SLIM_OP_ES || G.op == SLIM_OP_SPECTRAL;
+  }
+  // keep probability of the spectral scheme for entry (r, col[j])
+  __device__ double spectral_p(const Ctx& x, uint64_t j, uint32_t r) const {
+    const uint32_t c = col[j];
+    const int64_t dr = row_off[r + 1] - row_off[r], dc = row_off[c + 1] - row_off[c];
+    const double pe = x.ups / (double)(dr < dc ? dr : dc);
+    return pe > 1.0 ? 1.0 : pe;
+  }
   __device__ bool flag(const Ctx& x, uint64_t j, uint32_t r) const {
-    if (x.es) {
+    if (x.mode != 0) {
       const uint32_t c = col[j] - x.vb, rl = r - x.vb;
       const uint32_t a = c < rl ? c : rl, b = c < rl ? rl : c;
       uint32_t w0, w1;
-      philox_w01(a, b, 0u, 1u, x.k0, x.k1, w0, w1);
-      return !((uint64_t)w0 < x.thr);
+      if (x.mode == 1) {
+        philox_w01(a, b, 0u, 1u, x.k0, x.k1, w0, w1);
+        return !((uint64_t)w0 < x.thr);
+      }
+      const double pe = spectral_p(x, j, r);
+      const uint64_t thr = pe >= 1.0 ? (uint64_t(1) << 32) : (uint64_t)floor(pe * 4294967296.0);
+      philox_w01(a, b, 0u, 2u, x.k0, x.k1, w0, w1);
+      return (uint64_t)w0 < thr;
     }
     const uint32_t e = eid[j];
     return e >= m || !bit_get(del, e);  // e >= m only for inputs breaking the contract
   }
   __device__ uint32_t value(const Ctx& x, uint64_t j) const { return col[j] - x.vb; }
+  __device__ float weight(const Ctx& x, uint64_t j, uint32_t r) const {
+    return (float)(1.0 / spectral_p(x, j, r));
+  }
 };
 
 template <class P>
@@ -550,7 +576,12 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(P p, const int64_t* 
       const int c = w + k * kWavesPerBlock;
       const uint64_t j = (uint64_t)R.j0 + c * kWave + lane;
       const uint64_t pos = base + cbase[c] + __popcll(cmask[c] & lt);
-      if (pos < cap) out[pos] = p.value(x, j);  // always true for inputs that meet the contract
+      if (pos < cap) {  // always true for inputs that meet the contract
+        out[pos] = p.value(x, j);
+        if constexpr (P::kWeights)
+          if (G.out_w && G.op == SLIM_OP_SPECTRAL)
+            G.out_w[pos] = p.weight(x, j, tile_row_of(L, c * kWave + lane));
+      }
     }
   }
   const uint32_t total = cbase[kChunks];
@@ -611,7 +642,7 @@ void compact_out(const int64_t* row_off, const uint32_t* col, const uint32_t* ei
                  const uint32_t* del, uint64_t m, const GDesc* gd, const uint64_t* tile0,
                  const TileRec* recs, uint64_t ntiles, uint32_t* tile_cnt, uint64_t* tile_base,
                  uint64_t* scan_tmp, hipStream_t s) {
-  OutPolicy p{col, eid, del, m};
+  OutPolicy p{col, eid, del, row_off, m};
   compact<OutPolicy, OutPolicy, int64_t>(p, p, row_off, gd, tile0, recs, ntiles, tile_cnt,
                                          tile_base, scan_tmp, s);
 }

@@ -215,7 +215,8 @@ int run_batch(slim_server* S, Worker& W, const std::vector<Job*>& batch) {
     GDesc& d = gs[i];
     d.nv = J.n;
     d.ne = J.nnz;
-    d.thr = threshold(J.p);
+    d.thr = J.op == SLIM_OP_SPECTRAL ? 0 : threshold(J.p);
+    d.ups = J.op == SLIM_OP_SPECTRAL ? J.p : 0.0;
     d.k0 = (uint32_t)J.seed;
     d.k1 = (uint32_t)(J.seed >> 32);
     d.op = (uint32_t)J.op;
@@ -391,7 +392,7 @@ int slim_serve_submit(slim_server_t* S, const slim_job_t* job, uint64_t* ticket)
   const slim_job_t& J = *job;
   if (!op_valid(J.op) || J.pad || J.pad2)
     return fail(SLIM_EINVAL, "job: bad op %d", J.op);
-  if (check_p(J.p)) return SLIM_EINVAL;
+  if (check_param(J.op, J.p)) return SLIM_EINVAL;
   if (J.where != SLIM_HOST && J.where != SLIM_DEVICE)
     return fail(SLIM_EINVAL, "job: where must be SLIM_HOST or SLIM_DEVICE");
   if (!J.row_off || (J.nnz && !J.col)) return fail(SLIM_EINVAL, "job: NULL CSR array");

@@ -20,13 +20,13 @@ LIB_PATH = os.environ.get("SLIM_LIBRARY") or os.path.join(_HERE, "libslim.so")
 
 OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, EAGAIN = 0, -1, -2, -3, -4, -5
 VALIDATE = 1
-OP_TR, OP_ES, OP_TR2, OP_MCTR = 1, 2, 3, 4
+OP_TR, OP_ES, OP_TR2, OP_MCTR, OP_SPECTRAL = 1, 2, 3, 4, 5
 STAT_KEYS = ("n", "m_in", "triangles", "selected", "deleted", "m_out")
 
 # Exported symbols of libslim.so, in include/slim.h order.
 SYMBOLS = ("slim_last_error", "slim_strerror", "slim_version", "slim_load_csr",
            "slim_graph_free", "slim_workspace_size", "slim_triangle_reduce", "slim_edge_sample",
-           "slim_compress", "slim_batch_create", "slim_batch_workspace_size", "slim_batch_run", "slim_batch_set",
+           "slim_compress", "slim_spectral_sparsify", "slim_batch_create", "slim_batch_workspace_size", "slim_batch_run", "slim_batch_set",
            "slim_batch_get", "slim_batch_tune", "slim_batch_free",
            "slim_serve_create", "slim_serve_submit", "slim_serve_poll", "slim_serve_wait",
            "slim_serve_next", "slim_serve_cancel", "slim_serve_copy", "slim_result_release", "slim_serve_stats",
@@ -45,7 +45,7 @@ class JobParams(ctypes.Structure):
 
 class Out(ctypes.Structure):
     _fields_ = [("row_off", ctypes.c_void_p), ("col", ctypes.c_void_p),
-                ("stats", ctypes.c_void_p)]
+                ("stats", ctypes.c_void_p), ("weight", ctypes.c_void_p)]
 
 
 class ServeCfg(ctypes.Structure):
@@ -114,6 +114,8 @@ def _bind(path: str = LIB_PATH):
         fn.argtypes = [vp, dbl, u64, vp, u64, vp, vp, vp, vp]
     lib.slim_compress.restype = i32
     lib.slim_compress.argtypes = [vp, i32, dbl, u64, vp, u64, vp, vp, vp, vp]
+    lib.slim_spectral_sparsify.restype = i32
+    lib.slim_spectral_sparsify.argtypes = [vp, dbl, u64, vp, u64, vp, vp, vp, vp, vp]
     lib.slim_batch_create.restype = i32
     lib.slim_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(JobParams), u32,
                                       ctypes.POINTER(vp)]
@@ -274,6 +276,8 @@ class Buffers:
         self.out_row_off = torch.empty(g.n + 1, dtype=torch.int64, device=dev)
         self.out_col = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=dev)
         self.stats = torch.zeros(len(STAT_KEYS), dtype=torch.int64, device=dev)
+        self.out_w = (torch.empty(max(g.nnz, 1), dtype=torch.float32, device=dev)
+                      if op == OP_SPECTRAL else None)
 
 
 def _run(fn, g: Graph, p: float, seed: int, bufs: Buffers | None, stream):
@@ -308,6 +312,28 @@ def compress(g: Graph, op: int, p: float, seed: int, bufs: Buffers | None = None
                                 bufs.stats.data_ptr(), _stream_handle(stream, g.device))
     _check(rc)
     return bufs
+
+
+def spectral_sparsify(g: Graph, upsilon: float, seed: int, bufs: Buffers | None = None,
+                      stream=None):
+    """Enqueue spectral sparsification; the weights land in bufs.out_w."""
+    if bufs is None:
+        bufs = Buffers(g, OP_SPECTRAL)
+    with torch.cuda.device(g.device):
+        rc = _lib.slim_spectral_sparsify(
+            g._h, float(upsilon), int(seed) & (2**64 - 1), bufs.ws.data_ptr(), bufs.ws_bytes,
+            bufs.out_row_off.data_ptr(), bufs.out_col.data_ptr(),
+            bufs.out_w.data_ptr() if bufs.out_w is not None else None, bufs.stats.data_ptr(),
+            _stream_handle(stream, g.device))
+    _check(rc)
+    return bufs
+
+
+def weights_numpy(bufs: Buffers):
+    """Synchronise and copy the output weights of a spectral sparsification."""
+    torch.cuda.synchronize(bufs.g.device)
+    k = int(bufs.out_row_off[-1].item())
+    return bufs.out_w[:k].cpu().numpy()
 
 
 def result_numpy(bufs: Buffers):
@@ -352,11 +378,16 @@ class Batch:
         self.row_off_all = torch.empty(int(self.ro_base[-1]), dtype=torch.int64, device=dev)
         self.col_all = torch.empty(max(int(self.col_base[-1]), 1), dtype=torch.int32, device=dev)
         self.stats_all = torch.zeros((len(graphs), len(STAT_KEYS)), dtype=torch.int64, device=dev)
+        self.w_all = (torch.empty(max(int(self.col_base[-1]), 1), dtype=torch.float32, device=dev)
+                      if any(int(op) == OP_SPECTRAL for op, _, _ in jobs) else None)
         rp, cp, sp = (self.row_off_all.data_ptr(), self.col_all.data_ptr(),
                       self.stats_all.data_ptr())
+        wp = self.w_all.data_ptr() if self.w_all is not None else None
         self._outs = (Out * len(graphs))(*[
             Out(rp + 8 * int(self.ro_base[i]), cp + 4 * int(self.col_base[i]) if nnzs[i] else None,
-                sp + 8 * len(STAT_KEYS) * i) for i in range(len(graphs))])
+                sp + 8 * len(STAT_KEYS) * i,
+                wp + 4 * int(self.col_base[i]) if (wp and nnzs[i]) else None)
+            for i in range(len(graphs))])
 
     def __len__(self):
         return len(self.graphs)

@@ -66,6 +66,31 @@ def test_batch_all_operations_mixed(slim):
     check_batch(slim, graphs, mc_only, oracle_idx=[0, 3, len(graphs) - 1])
 
 
+def test_batch_spectral_weights(slim):
+    """Spectral sparsification jobs (p carries upsilon) beside TR jobs: CSR
+    and float32 weights equal the single-graph call bit for bit."""
+    import torch
+    from oracle import oracle as O
+    graphs = gg.batch_mix(10, 21, 1000, 8000)
+    jobs = [(slim.OP_SPECTRAL if i % 2 else slim.OP_TR, 2.5 if i % 2 else 0.5, i)
+            for i in range(len(graphs))]
+    dgs = [slim.Graph.from_csr(g) for g in graphs]
+    b = slim.Batch(dgs, jobs)
+    b.run()
+    torch.cuda.synchronize()
+    for i, (g, (op, p, seed)) in enumerate(zip(graphs, jobs)):
+        ro, col, st = b.result_numpy(i)
+        if op == slim.OP_SPECTRAL:
+            oro, ocol, ow, ost = O.spectral_sparsify(g, p, seed)
+            assert np.array_equal(ro, oro) and np.array_equal(col, ocol)
+            c0 = int(b.col_base[i])
+            w = b.w_all[c0:c0 + len(col)].cpu().numpy()
+            assert np.array_equal(w.view(np.uint32), ow.view(np.uint32))
+            assert st["deleted"] == ost["deleted"]
+        else:
+            assert_same((ro, col, st), oracle_run(g, "tr", p, seed))
+
+
 def test_batch_same_graph_many_seeds(slim):
     g = gg.er(2000, 16.0, 1)
     dg = slim.Graph.from_csr(g)

@@ -33,8 +33,8 @@ def slim(gpu):
 
 def gpu_run(slim, g, op, p, seed, validate=True):
     dg = slim.Graph.from_csr(g, validate=validate)
-    fn = slim.triangle_reduce if op == "tr" else slim.edge_sample
-    return slim.result_numpy(fn(dg, p, seed))
+    code = {"tr": slim.OP_TR, "es": slim.OP_ES, "tr2": slim.OP_TR2, "mctr": slim.OP_MCTR}[op]
+    return slim.result_numpy(slim.compress(dg, code, p, seed))
 
 
 def oracle_run(g, op, p, seed):
@@ -234,6 +234,13 @@ def test_rmat20_tr_full(slim, rmat20, p):
     _check_sampled_rows(rmat20, ro, col, p, 1, rows)
 
 
+@pytest.mark.parametrize("variant", ["tr2", "mctr"])
+def test_rmat20_variants_full(slim, rmat20, variant):
+    """R-MAT scale 20: Triangle p-2 and Min-Count p-1 Reduction against the
+    oracle's stored digests."""
+    _check_digest(slim, rmat20, f"rmat20_{variant}_p0.5")
+
+
 def test_rmat20_es_full(slim, rmat20):
     assert_same(gpu_run(slim, rmat20, "es", 0.5, 1, validate=False),
                 oracle_run(rmat20, "es", 0.5, 1))
@@ -316,3 +323,42 @@ def test_variants_schedule_independence(slim, knobs):
     finally:
         for k, v in old.items():
             slim.tune_set(k, v)
+
+
+# ------------------------------------------------- spectral sparsification
+
+def oracle_spectral(g, ups, seed):
+    ro, col, w, st = O.spectral_sparsify(g, ups, seed)
+    return (ro, col, {"n": st["n"], "m_in": st["m_in"], "triangles": 0, "selected": 0,
+                      "deleted": st["deleted"], "m_out": st["m_out"]}), w
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_spectral_small_graphs(slim, name):
+    """Output CSR, counters and every float32 weight bit for bit."""
+    g = SMALL[name]()
+    dg = slim.Graph.from_csr(g)
+    for ups, seed in ((1.0, 1), (0.0, 2), (3.5, 3), (1e9, 4), (0.37, 2**40 + 5)):
+        bufs = slim.spectral_sparsify(dg, ups, seed)
+        want, w = oracle_spectral(g, ups, seed)
+        assert_same(slim.result_numpy(bufs), want, f"{name} ups={ups}")
+        assert np.array_equal(slim.weights_numpy(bufs).view(np.uint32), w.view(np.uint32))
+
+
+def test_spectral_rmat20(slim, rmat20):
+    """R-MAT scale 20 (~31M CSR entries, hubs of degree > 10^4): upsilon =
+    p m / n with p = 0.5 (the paper's average-degree choice)."""
+    ups = 0.5 * rmat20.m / rmat20.n
+    dg = slim.Graph.from_csr(rmat20)
+    bufs = slim.spectral_sparsify(dg, ups, 1)
+    want, w = oracle_spectral(rmat20, ups, 1)
+    assert_same(slim.result_numpy(bufs), want)
+    assert np.array_equal(slim.weights_numpy(bufs).view(np.uint32), w.view(np.uint32))
+
+
+def test_spectral_bad_upsilon(slim):
+    dg = slim.Graph.from_csr(gg.complete(5))
+    for bad in (float("nan"), -0.5):
+        with pytest.raises(slim.SlimError) as e:
+            slim.spectral_sparsify(dg, bad, 1)
+        assert e.value.code == slim.EINVAL
