@@ -29,14 +29,14 @@
  *       kernel instances run once, concurrently (section 4.5, runtime
  *       listing `lst:general`: a single `run_kernels` pass); deleting an
  *       already deleted edge is a no-op.
- *   R5  Triangle p-2-Reduction (section 4.3: x in {1,2} edges of a selected
+ *   R8  Triangle p-2-Reduction (section 4.3: x in {1,2} edges of a selected
  *       triangle are removed, chosen u.a.r.): the two removed edges are the
  *       ones other than edge k of R4, i.e. the kept edge is uniform.
- *   R6  Min-Count Triangle p-1-Reduction (section 4.3): t_e = triangles of
+ *   R9  Min-Count Triangle p-1-Reduction (section 4.3): t_e = triangles of
  *       the input graph that contain e; a selected triangle removes its
  *       edge of smallest t_e, ties broken uniformly by word x1 among the
  *       tied edges in the order of R4.
- *   R7  Spectral sparsification (section 4.2.1, kernel spectral_sparsify):
+ *   R10 Spectral sparsification (section 4.2.1, kernel spectral_sparsify):
  *       the kernel keeps an edge when rand <= p_uv, so p_uv is the keep
  *       probability; upsilon is passed in directly (the paper suggests
  *       p log n or p m/n); the counter domain of the edge draw is (u,v,0,2).
@@ -344,10 +344,10 @@ int orc_triangle_reduce(uint64_t n, const int64_t* row_off, const uint32_t* col,
  * variant 1: p-1 (as orc_triangle_reduce); variant 2: Triangle
  * p-2-Reduction, where a selected triangle loses x = 2 of its edges chosen
  * uniformly, i.e. keeps the one edge k = floor(x1 * 3 / 2^32) and loses the
- * other two (R5); variant 3: Min-Count Triangle p-1-Reduction, where a
+ * other two (R8); variant 3: Min-Count Triangle p-1-Reduction, where a
  * selected triangle loses the edge that lies in the fewest triangles of the
  * input graph, ties broken uniformly: among the tied edges, in the order
- * {a,b}, {a,c}, {b,c}, the one at index floor(x1 * ties / 2^32) (R6).
+ * {a,b}, {a,c}, {b,c}, the one at index floor(x1 * ties / 2^32) (R9).
  * stats as orc_triangle_reduce.
  */
 typedef struct {
@@ -485,7 +485,7 @@ int orc_edge_sample(uint64_t n, const int64_t* row_off, const uint32_t* col, dou
  * p_uv = min(1, upsilon / min(d_u, d_v)) (degrees of the input graph) and a
  * kept edge gets weight 1/p_uv.  Decided once per edge from counter
  * (u,v,0,2): kept iff word 0 < floor(p_uv * 2^32) (2^32 when p_uv = 1), with
- * p_uv computed in double precision (R7).  out_w (float, may be NULL) gets the
+ * p_uv computed in double precision (R10).  out_w (float, may be NULL) gets the
  * weight of every output entry, (float)(1.0 / p_uv).  stats as
  * orc_edge_sample.  upsilon must be >= 0 (NaN -> -1).
  */
