@@ -335,7 +335,9 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
         hi = mid;
     }
     const uint32_t e = lo;  // dag_col[e] == x
-    const uint32_t beg = fe > fs ? e + 1 : yr.y;  // out(x) empty: no triangle, no scan
+    // out(x) empty: no triangle, no scan (e == yr.y only for inputs that
+    // break the CSR contract: then nothing is scanned either)
+    const uint32_t beg = fe > fs && e < yr.y ? e + 1 : yr.y;
     cnt = yr.y - beg;
     xtag = all_rows ? (fs - C.D0) : 0u;
     S.ie[tid] = make_uint4(beg, x, c, r);
