@@ -390,25 +390,45 @@ def main():
                      "scan_bytes_per_s": 4 * work["sum_out_pairs"] / (tri_ms * 1e-3)},
         "step_algorithmic_gbs": step_bytes(g, work, stats["m_out"]) / (ms_per_step * 1e-3) / 1e9,
     }
-    # the other triangle operations on the same graph (Triangle p-2-Reduction,
-    # Min-Count p-1-Reduction: counting pass + selection pass)
-    variants = {}
-    for name, op in (("tr2", slim.OP_TR2), ("mctr", slim.OP_MCTR)):
+    # the other operations on the same graph, each timed, and the scalar
+    # accuracy metric A_S = T_out / T_in of its output (section 5): triangles
+    # of the output counted by Triangle p-1-Reduction with p = 0 on the device
+    def triangles_of(bufs_out):
+        k = int(bufs_out.out_row_off[-1].item())
+        og = slim.Graph(bufs_out.out_row_off, bufs_out.out_col[:k])
+        ob = slim.triangle_reduce(og, 0.0, 1)
+        torch.cuda.synchronize()
+        t = int(ob.stats[2].item())
+        del ob, og
+        return t
+
+    t_in = stats["triangles"]
+    ups = args.p * g.m / g.n  # upsilon = p m / n, the paper's average-degree choice
+    variants = {"tr": {"ms": ms_per_step, "edges_per_s": g.m / (ms_per_step * 1e-3),
+                       "stats": stats}}
+    variants["tr"]["A_S_triangles"] = triangles_of(bufs) / t_in
+    for name, op in (("tr2", slim.OP_TR2), ("mctr", slim.OP_MCTR), ("es", slim.OP_ES),
+                     ("spectral", slim.OP_SPECTRAL)):
         vb = slim.Buffers(dg, op)
-        slim.compress(dg, op, args.p, args.seed, vb)
+        param = ups if op == slim.OP_SPECTRAL else args.p
+        slim.compress(dg, op, param, args.seed, vb)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         reps = 3
         for _ in range(reps):
-            slim.compress(dg, op, args.p, args.seed, vb)
+            slim.compress(dg, op, param, args.seed, vb)
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         vst = dict(zip(slim.STAT_KEYS, (int(x) for x in vb.stats.cpu().numpy())))
-        variants[name] = {"ms": ms, "edges_per_s": g.m / (ms * 1e-3), "stats": vst}
-        log(f"{name}: {ms:.2f} ms {vst}")
+        variants[name] = {"ms": ms, "edges_per_s": g.m / (ms * 1e-3), "stats": vst,
+                          "A_S_triangles": triangles_of(vb) / t_in}
+        if op == slim.OP_SPECTRAL:
+            variants[name]["upsilon"] = ups
+        log(f"{name}: {ms:.2f} ms {vst} A_S={variants[name]['A_S_triangles']:.4f}")
         del vb
+    variants["triangles_per_vertex_in"] = 3 * t_in / g.n
     result["variants"] = variants
     del bufs, es_bufs, dg
     torch.cuda.empty_cache()
