@@ -41,9 +41,9 @@ constexpr int kBucketBits = 11;
 constexpr int kBatch = 320;          // in-edges per batch
 constexpr int kQ = 128;              // per-wave hit queue (records)
 #ifndef SLIM_TRI_UNROLL
-#define SLIM_TRI_UNROLL 4
+#define SLIM_TRI_UNROLL 8
 #endif
-constexpr int kUnroll = SLIM_TRI_UNROLL;  // windows of 64 items issued together
+constexpr int kUnroll = SLIM_TRI_UNROLL;  // windows of 64 items whose loads are in flight together
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 static_assert(kBatch <= kTB, "one thread per in-edge in the setup");
@@ -414,21 +414,17 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
       xb[u] = g;
       wv[u] = C.a.dag_col[t < we ? b + t : 0u];
     }
-    // Probe: the home bucket and the next one (four slots, read together for
-    // all windows); a key can only sit further on if both are full.
-    uint4 e0[kUnroll], e1[kUnroll];
-    uint32_t bk[kUnroll];
+    // Probe window by window: the home bucket and the next one (four slots,
+    // read together); a key can only sit further on if both are full.  The
+    // scan is bound by the latency of the dag_col loads, so the registers go
+    // to keeping many windows' loads in flight, not to batching the probes.
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      bk[u] = hbucket(wv[u], xb[u]);
-      e0[u] = S.hb[bk[u]];
-      e1[u] = S.hb[(bk[u] + 1) & (kBuckets - 1)];
-    }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+      const uint32_t bku = hbucket(wv[u], xb[u]);
+      const uint4 e = S.hb[bku];
+      const uint4 f = S.hb[(bku + 1) & (kBuckets - 1)];
       const uint32_t t = wb + u * kWave + lane, wq = wv[u], g = xb[u];
       const bool valid = kk[u] != 0xffffu;
-      const uint4 e = e0[u], f = e1[u];
       const bool m0 = (e.x == wq) & ((e.y & 0xffffu) == g);
       const bool m1 = (e.z == wq) & ((e.w & 0xffffu) == g);
       const bool m2 = (f.x == wq) & ((f.y & 0xffffu) == g);
@@ -436,7 +432,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
       bool hit = valid & (m0 | m1 | m2 | m3);
       uint32_t qpos = (m0 ? e.y : m1 ? e.w : m2 ? f.y : f.w) >> 16;
       bool more = valid & !(m0 | m1 | m2 | m3) & (e.z != kEmpty) & (f.z != kEmpty);
-      uint32_t bkt = (bk[u] + 1) & (kBuckets - 1);
+      uint32_t bkt = (bku + 1) & (kBuckets - 1);
       if (__ballot(more)) {  // both buckets full: keep probing (rare)
         while (__ballot(more)) {
           if (more) {
