@@ -128,7 +128,9 @@ def triangle_reduce(g, p: float, seed: int):
 def triangle_reduce_x(g, p: float, seed: int, variant: int):
     """Triangle p-x-Reduction variants: 1 = p-1, 2 = p-2 (a selected triangle
     keeps one uniform edge), 3 = Min-Count p-1 (removes its edge in the fewest
-    input triangles, ties uniform).  Returns (row_off, col, stats)."""
+    input triangles, ties uniform), 4 = Edge-Once p-1 (selected triangles in
+    priority order; one is considered only if none of its edges has been).
+    Returns (row_off, col, stats)."""
     lib = _load()
 
     def fn(n, ro, col, p_, seed_, oro, ocol, st):

@@ -40,6 +40,17 @@
  *       the kernel keeps an edge when rand <= p_uv, so p_uv is the keep
  *       probability; upsilon is passed in directly (the paper suggests
  *       p log n or p m/n); the counter domain of the edge draw is (u,v,0,2).
+ *   R11 Edge-Once Triangle p-1-Reduction (section 4.3; the bounds of
+ *       section 6.2 need that every edge is considered at most once and
+ *       that no considered triangle loses two edges): the selected
+ *       triangles (R1) are taken one at a time in increasing priority
+ *       (x2, a, b, c), x2 being Philox output word 2 of the triangle's
+ *       counter (R4); a triangle is considered iff none of its three edges
+ *       is considered yet, and then deletes its edge k (R4) while all three
+ *       of its edges become considered.  The considered triangles are the
+ *       greedy maximal edge-disjoint set of selected triangles in priority
+ *       order.  (The listing's branch that sets `considered` is read as
+ *       applying to every considered triangle's edges.)
  *   R4  The random source `SG.rand` is unspecified in the paper; here it is
  *       Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
  *       key = (seed mod 2^32, seed div 2^32).  For the triangle {a<b<c}
@@ -347,8 +358,8 @@ int orc_triangle_reduce(uint64_t n, const int64_t* row_off, const uint32_t* col,
  * other two (R8); variant 3: Min-Count Triangle p-1-Reduction, where a
  * selected triangle loses the edge that lies in the fewest triangles of the
  * input graph, ties broken uniformly: among the tied edges, in the order
- * {a,b}, {a,c}, {b,c}, the one at index floor(x1 * ties / 2^32) (R9).
- * stats as orc_triangle_reduce.
+ * {a,b}, {a,c}, {b,c}, the one at index floor(x1 * ties / 2^32) (R9);
+ * variant 4: Edge-Once p-1 (R11, below).  stats as orc_triangle_reduce.
  */
 typedef struct {
   const orc_graph* g;
@@ -397,9 +408,112 @@ static void orc_trx_cb(void* vctx, uint32_t x, uint32_t y, uint32_t z) {
   }
 }
 
+/* ----------------------- Edge-Once Triangle p-1-Reduction (4.3, 6.2)
+ * variant 4 (R11): collect the selected triangles with their priority x2
+ * and edge choice k, sort them by (x2, a, b, c), then walk them in that
+ * order; a triangle none of whose edges is considered yet deletes edge k
+ * and marks its three edges considered, any other is skipped.
+ */
+typedef struct {
+  uint32_t pri, a, b, c, k;
+} orc_eo_tri;
+
+typedef struct {
+  uint64_t thr;
+  uint32_t key[2];
+  orc_eo_tri* sel;
+  uint64_t T, selected, cap;
+  int err;
+} orc_eo_ctx;
+
+static void orc_eo_cb(void* vctx, uint32_t x, uint32_t y, uint32_t z) {
+  orc_eo_ctx* c = (orc_eo_ctx*)vctx;
+  orc_sort3(&x, &y, &z);
+  uint32_t ctr[4] = {x, y, z, 0u};
+  uint32_t r[4];
+  orc_philox4x32_10(ctr, c->key, r);
+  c->T++;
+  if ((uint64_t)r[0] >= c->thr) return;
+  if (c->selected == c->cap) {
+    uint64_t cap = c->cap ? 2 * c->cap : 1024;
+    orc_eo_tri* s = (orc_eo_tri*)realloc(c->sel, cap * sizeof(orc_eo_tri));
+    if (!s) {
+      c->err = 1;
+      return;
+    }
+    c->sel = s;
+    c->cap = cap;
+  }
+  orc_eo_tri t = {r[2], x, y, z, (uint32_t)(((uint64_t)r[1] * 3u) >> 32)};
+  c->sel[c->selected++] = t;
+}
+
+static int orc_eo_cmp(const void* pa, const void* pb) {
+  const orc_eo_tri* a = (const orc_eo_tri*)pa;
+  const orc_eo_tri* b = (const orc_eo_tri*)pb;
+  if (a->pri != b->pri) return a->pri < b->pri ? -1 : 1;
+  if (a->a != b->a) return a->a < b->a ? -1 : 1;
+  if (a->b != b->b) return a->b < b->b ? -1 : 1;
+  if (a->c != b->c) return a->c < b->c ? -1 : 1;
+  return 0;
+}
+
+static int orc_triangle_reduce_eo(uint64_t n, const int64_t* row_off, const uint32_t* col,
+                                  double p, uint64_t seed, int64_t* out_row_off,
+                                  uint32_t* out_col, uint64_t* stats) {
+  orc_graph g = {n, row_off, col};
+  uint64_t nnz = (uint64_t)row_off[n];
+  orc_eo_ctx c;
+  memset(&c, 0, sizeof(c));
+  if (orc_threshold(p, &c.thr)) return -1;
+  c.key[0] = (uint32_t)seed;
+  c.key[1] = (uint32_t)(seed >> 32);
+  if (orc_for_each_triangle(&g, orc_eo_cb, &c) || c.err) {
+    free(c.sel);
+    return -3;
+  }
+  if (c.selected > 1) qsort(c.sel, c.selected, sizeof(orc_eo_tri), orc_eo_cmp);
+  uint8_t* del = (uint8_t*)calloc(nnz > 0 ? nnz : 1, 1);
+  uint8_t* considered = (uint8_t*)calloc(nnz > 0 ? nnz : 1, 1);
+  int err = !del || !considered;
+  for (uint64_t i = 0; i < c.selected && !err; ++i) {
+    const orc_eo_tri* t = &c.sel[i];
+    /* the edges in the order of R4: {a,b}, {a,c}, {b,c} */
+    int64_t slot[3] = {orc_edge_slot(&g, t->a, t->b), orc_edge_slot(&g, t->a, t->c),
+                       orc_edge_slot(&g, t->b, t->c)};
+    if (slot[0] < 0 || slot[1] < 0 || slot[2] < 0) {
+      err = 1;
+      break;
+    }
+    if (considered[slot[0]] || considered[slot[1]] || considered[slot[2]]) continue;
+    del[slot[t->k]] = 1;
+    considered[slot[0]] = considered[slot[1]] = considered[slot[2]] = 1;
+  }
+  free(c.sel);
+  free(considered);
+  if (err) {
+    const int rc = del ? -3 : -2;
+    free(del);
+    return rc;
+  }
+  uint64_t deleted = 0;
+  for (uint64_t j = 0; j < nnz; ++j) deleted += del[j];
+  orc_compact(&g, del, out_row_off, out_col);
+  free(del);
+  stats[0] = n;
+  stats[1] = nnz / 2;
+  stats[2] = c.T;
+  stats[3] = c.selected;
+  stats[4] = deleted;
+  stats[5] = nnz / 2 - deleted;
+  return 0;
+}
+
 int orc_triangle_reduce_x(uint64_t n, const int64_t* row_off, const uint32_t* col, double p,
                           uint64_t seed, int variant, int64_t* out_row_off, uint32_t* out_col,
                           uint64_t* stats) {
+  if (variant == 4)
+    return orc_triangle_reduce_eo(n, row_off, col, p, seed, out_row_off, out_col, stats);
   if (variant < 1 || variant > 3) return -4;
   orc_graph g = {n, row_off, col};
   uint64_t nnz = (uint64_t)row_off[n];

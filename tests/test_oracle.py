@@ -470,6 +470,127 @@ def test_min_count_deletes_only_minimal_edges(cfg1):
     assert st["deleted"] <= st["selected"] == st["T"]
 
 
+# ------------------------------------------ Edge-Once p-1-Reduction
+
+def brute_eo(g, p, seed):
+    """Edge-Once p-1 on tiny graphs by rounds of local minima instead of the
+    oracle's sorted walk: every undecided selected triangle whose priority
+    (x2, a, b, c) is below that of every other undecided selected triangle
+    sharing an edge with it is considered; triangles sharing an edge with a
+    considered one are dropped; repeat.  With fixed priorities these rounds
+    reach the same set as the greedy walk in priority order (the
+    lexicographically first maximal independent set of the conflict graph),
+    so agreement checks the walk by a different algorithm."""
+    thr = O.threshold(p)
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    tris = sorted(brute_triangles(g))
+    pri, kk = {}, {}
+    for t in tris:
+        w = O.philox4x32_10((*t, 0), key)
+        if w[0] < thr:
+            pri[t] = (w[2], t)
+            kk[t] = (w[1] * 3) >> 32
+
+    def edges(t):
+        x, y, z = t
+        return [(x, y), (x, z), (y, z)]
+
+    und, taken, dele, rounds = set(pri), set(), set(), 0
+    while und:
+        rounds += 1
+        best = {}
+        for t in und:
+            for e in edges(t):
+                best[e] = min(best.get(e, pri[t]), pri[t])
+        win = [t for t in und if all(best[e] == pri[t] for e in edges(t))]
+        assert win  # the undecided triangle of lowest priority always wins
+        for t in win:
+            dele.add(edges(t)[kk[t]])
+            taken |= set(edges(t))
+        und = {t for t in und if t not in win and not (set(edges(t)) & taken)}
+    keep = undirected(g.row_off, g.col) - dele
+    return keep, len(tris), len(pri), len(dele), rounds
+
+
+@pytest.mark.parametrize("n,q,seed", [(9, 0.6, 1), (12, 0.5, 2), (14, 0.45, 3), (10, 0.8, 4),
+                                      (16, 0.7, 5)])
+def test_eo_matches_rounds_of_local_minima(n, q, seed):
+    g = gg.er(n, q * (n - 1), seed)
+    for p, s in ((1.0, 7), (0.5, 8), (0.7, 2**40 + 3), (0.9, 11)):
+        ro, col, st = O.triangle_reduce_x(g, p, s, 4)
+        keep, t, sel, nd, _ = brute_eo(g, p, s)
+        assert undirected(ro, col) == keep and is_valid_csr(g.n, ro, col)
+        assert (st["T"], st["selected"], st["deleted"]) == (t, sel, nd)
+
+
+def test_eo_equals_p1_on_edge_disjoint_triangles():
+    """Friendship graph F_k: no two triangles share an edge, so every
+    selected triangle is considered and Edge-Once p-1 is plain p-1."""
+    g = gg.friendship(200)
+    for p, s in ((0.5, 1), (1.0, 2), (0.3, 3)):
+        a, b = O.triangle_reduce(g, p, s), O.triangle_reduce_x(g, p, s, 4)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
+def test_eo_k4_deletes_one_edge_of_the_first_triangle():
+    """K4 with p = 1: its four triangles pairwise share an edge, so only the
+    triangle of lowest priority (Philox word 2, then ids) is considered and
+    exactly its edge k goes."""
+    g = gg.complete(4)
+    for s in range(30):
+        key = (s & 0xFFFFFFFF, s >> 32)
+        ws = {t: O.philox4x32_10((*t, 0), key) for t in itertools.combinations(range(4), 3)}
+        first = min(ws, key=lambda t: (ws[t][2], t))
+        x, y, z = first
+        gone = [(x, y), (x, z), (y, z)][(ws[first][1] * 3) >> 32]
+        ro, col, st = O.triangle_reduce_x(g, 1.0, s, 4)
+        assert undirected(g.row_off, g.col) - undirected(ro, col) == {gone}
+        assert (st["T"], st["selected"], st["deleted"]) == (4, 4, 1)
+
+
+def test_eo_p0_is_identity(cfg1):
+    ro, col, st = O.triangle_reduce_x(cfg1, 0.0, 3, 4)
+    assert np.array_equal(ro, cfg1.row_off) and np.array_equal(col, cfg1.col)
+    assert st["selected"] == 0 and st["deleted"] == 0
+
+
+@pytest.mark.parametrize("p,seed", [(1.0, 1), (0.5, 2)])
+def test_eo_output_is_a_2_spanner(cfg1, p, seed):
+    """Section 6.2: at most one edge goes per considered triangle and no
+    edge is considered twice, so every deleted {u,v} keeps a path u-w-v of
+    two surviving edges (the rest of its triangle), and at most m/3 edges go."""
+    ro, col, st = O.triangle_reduce_x(cfg1, p, seed, 4)
+    kept = undirected(ro, col)
+    gone = undirected(cfg1.row_off, cfg1.col) - kept
+    nb = {}
+    for a, b in kept:
+        nb.setdefault(a, set()).add(b)
+        nb.setdefault(b, set()).add(a)
+    assert gone and len(gone) == st["deleted"] <= st["m_in"] // 3
+    for u, v in gone:
+        assert nb.get(u, set()) & nb.get(v, set()), (u, v)
+
+
+def test_eo_removes_no_more_than_one_edge_per_triangle_it_considers():
+    """Two triangles sharing an edge (a diamond) with p = 1: only the one of
+    lower priority is considered, so exactly one edge goes, never two."""
+    g = gg.from_pairs(4, [(0, 1), (0, 2), (1, 2), (1, 3), (2, 3)])
+    for s in range(40):
+        ro, col, st = O.triangle_reduce_x(g, 1.0, s, 4)
+        assert st["deleted"] == 1 and len(undirected(ro, col)) == 4
+
+
+def test_eo_edge_count_bound_of_table_theory():
+    """The Edge-Once row of the schemes table bounds the edge count by
+    m - pT/(3d) in expectation (d the maximum degree): the mean number of
+    deleted edges over seeds is at least pT/(3d)."""
+    g = gg.rmat(11, 8, 2)
+    d = int(np.max(np.diff(g.row_off)))
+    for p in (0.3, 0.8):
+        sts = [O.triangle_reduce_x(g, p, s, 4)[2] for s in range(8)]
+        assert np.mean([x["deleted"] for x in sts]) >= p * sts[0]["T"] / (3 * d)
+
+
 # ------------------------------------------------- spectral sparsification
 
 def _pe(g, a, b, ups):
