@@ -84,6 +84,7 @@ SLIM_API void slim_graph_free(slim_graph_t* g);
 #define SLIM_OP_TR2 3  /* Triangle p-2-Reduction */
 #define SLIM_OP_MCTR 4 /* Min-Count Triangle p-1-Reduction */
 #define SLIM_OP_SPECTRAL 5 /* spectral sparsification (p carries upsilon) */
+#define SLIM_OP_EOTR 6 /* Edge-Once Triangle p-1-Reduction */
 
 /* Device workspace (bytes) that `op` needs on graph `g`. */
 SLIM_API int slim_workspace_size(const slim_graph_t* g, int op, uint64_t* bytes);
@@ -152,6 +153,25 @@ SLIM_API int slim_edge_sample(const slim_graph_t* g, double p, uint64_t seed, vo
  *                 floor(word1 * ties / 2^32).
  *   SLIM_OP_SPECTRAL  as slim_spectral_sparsify with upsilon = p (any value
  *                 >= 0) and no weights.
+ *   SLIM_OP_EOTR  Edge-Once Triangle p-1-Reduction (section 4.3; the
+ *                 conditions of section 6.2: an edge is considered for
+ *                 deletion at most once, a considered triangle loses one
+ *                 edge).  Triangles are selected as by slim_triangle_reduce
+ *                 and ordered by priority (word 2 of the same Philox
+ *                 output, then the ids a, b, c).  In that order a selected
+ *                 triangle is considered iff none of its three edges is
+ *                 considered yet; it then deletes edge k and its three edges
+ *                 become considered.  The output is the same as that
+ *                 sequential walk: the GPU reaches it in rounds, each
+ *                 considering every selected triangle that is first in
+ *                 priority among the undecided ones sharing an edge with it.
+ *                 The number of rounds depends on the data: the call
+ *                 synchronises `stream` (after each "eo_rounds" rounds, see
+ *                 slim_tune_set) and returns when the output is complete;
+ *                 so do batch runs and server batches holding such a job.  Every deleted edge
+ *                 keeps a two-edge path (the output is a 2-spanner).
+ *                 selected counts the Bernoulli selections, deleted the
+ *                 considered triangles.
  */
 SLIM_API int slim_compress(const slim_graph_t* g, int op, double p, uint64_t seed, void* d_ws,
                            uint64_t ws_bytes, int64_t* d_out_row_off, uint32_t* d_out_col,
@@ -193,7 +213,7 @@ SLIM_API int slim_spectral_sparsify(const slim_graph_t* g, double upsilon, uint6
  * refreshes with one host-to-device copy when they change).
  */
 typedef struct slim_job_params {
-  int32_t op;    /* SLIM_OP_TR, SLIM_OP_ES, SLIM_OP_TR2 or SLIM_OP_MCTR */
+  int32_t op;    /* any SLIM_OP_* code (SLIM_OP_SPECTRAL: p carries upsilon) */
   int32_t pad;   /* must be 0 */
   double p;      /* as slim_compress */
   uint64_t seed; /* as slim_triangle_reduce / slim_edge_sample */
@@ -361,6 +381,8 @@ SLIM_API void slim_serve_destroy(slim_server_t* s);
  *   "tri_chunk"          out(x) entries hashed in LDS per pass, 32..2048
  *   "tri_blocks_per_cu"  resident blocks per CU of the triangle kernel, 1..64
  *   "tri_tile"           CSR entries per triangle work tile: 256, 512 or 1024
+ *   "eo_rounds"          Edge-Once rounds enqueued before the host checks
+ *                        whether more are needed, 1..64 (default 16)
  * Unknown key or value out of range -> SLIM_EINVAL.
  */
 SLIM_API int slim_tune_set(const char* key, int64_t value);

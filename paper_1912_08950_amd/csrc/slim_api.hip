@@ -108,6 +108,8 @@ SetShape single_shape(uint64_t n, uint64_t nnz, int op) {
   S.NNZ = nnz;
   S.gathered = false;
   S.has_tr = op_lists_triangles((uint32_t)op);
+  S.has_eo = op == SLIM_OP_EOTR;
+  S.has_list = S.has_tr && !S.has_eo;
   S.general = op == SLIM_OP_TR2 || op == SLIM_OP_MCTR;
   S.has_mc = op == SLIM_OP_MCTR;
   S.n_c = tiles_of(nnz, kTile);
@@ -167,6 +169,11 @@ SetLayout set_layout(const SetShape& S) {
     L.sort_counts = c.take<uint32_t>(4);
     L.tri_ctr = c.take<uint32_t>(4);
     if (S.has_mc) L.tcount = c.take<uint32_t>(m);
+    if (S.has_eo) {
+      L.minkey = c.take<uint64_t>(m);
+      L.closed = c.take<uint32_t>(ceil_div(m, 32) + 1);
+      L.eo_und = c.take<uint64_t>(kEoMaxRounds + 1);
+    }
   }
   L.scan_tmp = c.take<uint64_t>(st + 1);
   L.total = c.off;
@@ -236,6 +243,46 @@ void prof_end(bool on, hipStream_t s) {
 }
 
 // ------------------------------------------------------ the pipeline
+// Edge-Once rounds r0..r1 of a set (launches after the last busy round
+// return at once).
+void eo_rounds(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num_cu, void* ws,
+               TriArgs a, uint32_t r0, uint32_t r1, hipStream_t s) {
+  a.minkey = at<uint64_t>(ws, L.minkey);
+  a.closed = at<uint32_t>(ws, L.closed);
+  a.eo_und = at<uint64_t>(ws, L.eo_und);
+  for (uint32_t r = r0; r <= r1; ++r) {
+    eo_clear_bids(a.minkey, a.closed, S.NNZ / 2, a.eo_und, r, s);
+    a.round = r;
+    a.pass = 2;
+    triangles(a, kModeEO, at<uint32_t>(ws, L.tri_ctr), num_cu, knobs.tri_blocks_per_cu,
+              knobs.tri_chunk, s);
+    a.pass = 3;
+    triangles(a, kModeEO, at<uint32_t>(ws, L.tri_ctr), num_cu, knobs.tri_blocks_per_cu,
+              knobs.tri_chunk, s);
+  }
+}
+
+// The triangle kernel's arguments for a set whose DAG is in the workspace.
+TriArgs tri_args(const SetShape& S, const SetLayout& L, const Tuning& knobs, void* ws,
+                 const int64_t* row_off, const uint32_t* col, const uint32_t* order) {
+  TriArgs a{};
+  a.row_off = row_off;
+  a.col = col;
+  a.rank = at<uint32_t>(ws, L.rank);
+  a.rcol = at<uint32_t>(ws, L.rcol);
+  a.order = order;
+  a.dag_rng = at<uint2>(ws, L.dag_rng);
+  a.fstart = at<uint32_t>(ws, L.fstart);
+  a.dag_col = at<uint32_t>(ws, L.dag_col);
+  a.eid = at<uint32_t>(ws, L.eid);
+  a.del = at<uint32_t>(ws, L.del);
+  a.counters = at<uint64_t>(ws, L.counters);
+  a.gd = at<GDesc>(ws, L.gd);
+  a.recs = at<TileRec>(ws, L.recs_t);
+  a.ntiles = S.n_t(knobs.tri_tile);
+  a.tcount = S.has_mc ? at<uint32_t>(ws, L.tcount) : nullptr;
+  return a;
+}
 // Enqueues every phase of a set whose header (descriptors and tile
 // prefixes) is already in the workspace.  `row_off`/`col` are the caller's
 // CSR for a single graph; a gathered set builds its union in the workspace.
@@ -292,7 +339,7 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
     fill_u32(reinterpret_cast<uint32_t*>(counters), 4 * (uint64_t)S.count, 0, s);
     prof_end(profile, s);
     prof_begin(profile, "triangles", s);
-    TriArgs a;
+    TriArgs a{};
     a.row_off = row_off;
     a.col = col;
     a.rank = rank;
@@ -308,22 +355,71 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
     a.recs = recs_t;
     a.ntiles = n_t;
     a.tcount = S.has_mc ? at<uint32_t>(ws, L.tcount) : nullptr;
+    a.round = 0;
     if (S.has_mc) {  // Min-Count: per-edge triangle counts first
       fill_u32(a.tcount, S.NNZ / 2, 0, s);
       a.pass = 0;
-      triangles(a, true, at<uint32_t>(ws, L.tri_ctr), num_cu, knobs.tri_blocks_per_cu,
+      triangles(a, kModeGeneral, at<uint32_t>(ws, L.tri_ctr), num_cu, knobs.tri_blocks_per_cu,
                 knobs.tri_chunk, s);
     }
-    a.pass = 1;
-    triangles(a, S.general, at<uint32_t>(ws, L.tri_ctr), num_cu, knobs.tri_blocks_per_cu,
-              knobs.tri_chunk, s);
+    if (S.has_list) {
+      a.pass = 1;
+      triangles(a, S.general ? kModeGeneral : kModePlain, at<uint32_t>(ws, L.tri_ctr), num_cu,
+                knobs.tri_blocks_per_cu, knobs.tri_chunk, s);
+    }
     prof_end(profile, s);
+    if (S.has_eo) {
+      prof_begin(profile, "eo_rounds", s);
+      fill_u32(at<uint32_t>(ws, L.closed), ceil_div(S.NNZ / 2, 32) + 1, 0, s);
+      fill_u32(reinterpret_cast<uint32_t*>(at<uint64_t>(ws, L.eo_und)), 2 * (kEoMaxRounds + 1),
+               0, s);
+      eo_rounds(S, L, knobs, num_cu, ws, a, 1, (uint32_t)knobs.eo_rounds, s);
+      prof_end(profile, s);
+    }
     prof_begin(profile, "compact", s);
   }
   compact_out(row_off, col, eid, del, S.NNZ / 2, gd, t0c, recs_c, S.n_c, tile_cnt, tile_base,
               scan_tmp, s);
   write_stats(gd, S.count, t0c, counters, tile_base, s);
   prof_end(profile, s);
+}
+
+int eo_finish(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num_cu, void* ws,
+              const int64_t* row_off, const uint32_t* col, hipStream_t s) {
+  if (!S.has_eo || S.NNZ == 0) return SLIM_OK;
+  if (S.gathered) {
+    row_off = at<int64_t>(ws, L.urow);
+    col = at<uint32_t>(ws, L.ucol);
+  }
+  const uint64_t* und = at<uint64_t>(ws, L.eo_und);
+  const uint32_t step = (uint32_t)knobs.eo_rounds;
+  uint32_t last = step;
+  bool more = false;
+  for (;;) {
+    uint64_t u = 0;
+    if (hipMemcpyAsync(&u, und + last, sizeof(u), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(SLIM_EDEVICE, "Edge-Once round counter: %s",
+                  hipGetErrorString(hipGetLastError()));
+    if (u == 0) break;
+    if (last + step > kEoMaxRounds)
+      return fail(SLIM_EDEVICE, "Edge-Once: undecided triangles after %u rounds", last);
+    const uint32_t* order = at<uint32_t>(ws, S.passes % 2 ? L.vb : L.va);
+    eo_rounds(S, L, knobs, num_cu, ws, tri_args(S, L, knobs, ws, row_off, col, order), last + 1,
+              last + step, s);
+    last += step;
+    more = true;
+  }
+  if (more) {  // the first compaction saw the marks of the first rounds only
+    const GDesc* gd = at<GDesc>(ws, L.gd);
+    const uint64_t* t0c = at<uint64_t>(ws, L.t0c);
+    uint64_t* tile_base = at<uint64_t>(ws, L.tile_base);
+    compact_out(row_off, col, at<uint32_t>(ws, L.eid), at<uint32_t>(ws, L.del), S.NNZ / 2, gd,
+                t0c, at<TileRec>(ws, L.recs_c), S.n_c, at<uint32_t>(ws, L.tile_cnt), tile_base,
+                at<uint64_t>(ws, L.scan_tmp), s);
+    write_stats(gd, S.count, t0c, at<uint64_t>(ws, L.counters), tile_base, s);
+  }
+  return SLIM_OK;
 }
 
 // ----------------------------------------------------------- tuning
@@ -340,6 +436,9 @@ bool tune_apply(Tuning& t, const char* key, int64_t value) {
         (value & (value - 1)) != 0)
       return false;
     t.tri_tile = (int)value;
+  } else if (k == "eo_rounds") {
+    if (value < 1 || value > 64) return false;
+    t.eo_rounds = (int)value;
   } else {
     return false;
   }
@@ -354,6 +453,8 @@ bool tune_read(const Tuning& t, const char* key, int64_t* value) {
     *value = t.tri_blocks_per_cu;
   else if (k == "tri_tile")
     *value = t.tri_tile;
+  else if (k == "eo_rounds")
+    *value = t.eo_rounds;
   else
     return false;
   return true;
@@ -462,6 +563,8 @@ int single_op(int op, const slim_graph* g, double p, uint64_t seed, void* ws, ui
     return fail(SLIM_EDEVICE, "internal: set header layout");
   put_bytes(at<char>(ws, L.gd), &h, sizeof(h), s);
   run_set(S, L, knobs, g->num_cu, ws, g->row_off, g->col, s, true);
+  if (int rc = hip_check(what)) return rc;
+  if (int rc = eo_finish(S, L, knobs, g->num_cu, ws, g->row_off, g->col, s)) return rc;
   return hip_check(what);
 }
 

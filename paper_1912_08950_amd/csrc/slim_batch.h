@@ -24,9 +24,11 @@ struct SetShape {
   uint32_t count = 0;
   uint64_t N = 0, NNZ = 0;  // union vertices and CSR entries
   bool gathered = false;    // union built in the workspace (batches)
-  bool has_tr = false;      // some graph lists triangles (TR, TR2, MCTR)
-  bool general = false;     // some graph runs TR2 or MCTR (general triangle kernel)
+  bool has_tr = false;      // some graph lists triangles (TR, TR2, MCTR, EOTR)
+  bool has_list = false;    // some graph runs TR, TR2 or MCTR (the selection pass)
+  bool general = false;     // some graph runs TR2 or MCTR (general kernel for the selection pass)
   bool has_mc = false;      // some graph runs MCTR (counting pass)
+  bool has_eo = false;      // some graph runs EOTR (rounds of bids and acceptance)
   uint64_t n_c = 0;         // graph-aligned tiles of kTile entries (compaction)
   uint64_t n_u = 0;         // union tiles of kTile entries (orientation)
   uint64_t n_tri[3] = {0, 0, 0};  // graph-aligned triangle tiles of 256, 512, 1024 entries
@@ -44,6 +46,7 @@ struct SetLayout {
   uint64_t ka, va, kb, vb, rank, rcol, hist, hist_scan;
   uint64_t fstart, dag_rng, dag_col, eid, del, counters;
   uint64_t sort_lists, sort_counts, tri_ctr, tcount;
+  uint64_t minkey, closed, eo_und;
   uint64_t total;
 };
 
@@ -62,6 +65,12 @@ SetLayout set_layout(const SetShape& S);
 GDesc union_desc(const SetShape& S, const SetLayout& L, void* ws);
 void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num_cu, void* ws,
              const int64_t* row_off, const uint32_t* col, hipStream_t s, bool profile);
+// Sets with Edge-Once graphs: after run_set (or the replay of its capture)
+// on stream s, waits for s, runs further rounds while the last one still
+// found undecided triangles and then compacts again.  SLIM_OK at once for
+// other sets.
+int eo_finish(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num_cu, void* ws,
+              const int64_t* row_off, const uint32_t* col, hipStream_t s);
 void prof_reset();
 std::mutex& tuning_mutex();
 

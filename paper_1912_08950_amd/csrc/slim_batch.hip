@@ -45,6 +45,10 @@ int plan_set(const std::vector<GDesc>& graphs, SetPlan& P) {
     if (op_lists_triangles(d.op)) S.has_tr = true;
     if (d.op == SLIM_OP_TR2 || d.op == SLIM_OP_MCTR) S.general = true;
     if (d.op == SLIM_OP_MCTR) S.has_mc = true;
+    if (d.op == SLIM_OP_EOTR)
+      S.has_eo = true;
+    else if (op_lists_triangles(d.op))
+      S.has_list = true;
     uint64_t md = d.nv > 0 ? d.nv - 1 : 0;
     if (d.ne < md) md = d.ne;
     if (md > maxdeg) maxdeg = md;
@@ -118,7 +122,7 @@ namespace {
 
 bool same_knobs(const Tuning& a, const Tuning& b) {
   return a.tri_chunk == b.tri_chunk && a.tri_blocks_per_cu == b.tri_blocks_per_cu &&
-         a.tri_tile == b.tri_tile;
+         a.tri_tile == b.tri_tile && a.eo_rounds == b.eo_rounds;
 }
 
 void drop_graph(slim_batch* b) {
@@ -178,6 +182,9 @@ int run(slim_batch* b, void* ws, uint64_t ws_bytes, const slim_out_t* outs, hipS
   if (!b->use_graph) {  // direct launches: phases are timed when profiling is on
     prof_reset();
     run_set(b->plan.shape, b->layout, b->knobs, b->num_cu, ws, nullptr, nullptr, s, true);
+    if (int rc = hip_check("slim_batch_run")) return rc;
+    if (int rc = eo_finish(b->plan.shape, b->layout, b->knobs, b->num_cu, ws, nullptr, nullptr, s))
+      return rc;
     return hip_check("slim_batch_run");
   }
   if (!b->exec || b->cap_ws != ws || !same_knobs(b->cap_knobs, b->knobs)) {
@@ -202,6 +209,9 @@ int run(slim_batch* b, void* ws, uint64_t ws_bytes, const slim_out_t* outs, hipS
     b->cap_knobs = b->knobs;
   }
   if (hipGraphLaunch(b->exec, s) != hipSuccess) return fail(SLIM_EDEVICE, "hipGraphLaunch failed");
+  // Edge-Once rounds past the captured ones run as direct launches
+  if (int rc = eo_finish(b->plan.shape, b->layout, b->knobs, b->num_cu, ws, nullptr, nullptr, s))
+    return rc;
   return hip_check("slim_batch_run");
 }
 

@@ -48,11 +48,9 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
 // Counter-based random source: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
 // SC'11).  A round sends (x0,x1,x2,x3) under key (k0,k1) to
 // (hi(B*x2)^x1^k0, lo(B*x2), hi(A*x0)^x3^k1, lo(A*x0)) with A = 0xD2511F53,
-// B = 0xCD9E8D57; the key then moves on by (0x9E3779B9, 0xBB67AE85).  Only
-// output words 0 and 1 are used by the compression kernels.
-__device__ __forceinline__ void philox_w01(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
-                                           uint32_t k0, uint32_t k1, uint32_t& w0,
-                                           uint32_t& w1) {
+// B = 0xCD9E8D57; the key then moves on by (0x9E3779B9, 0xBB67AE85).
+__device__ __forceinline__ uint4 philox4(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                         uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     // one 32x32->64 product each (a single multiply-add instruction on gfx950)
@@ -65,8 +63,16 @@ __device__ __forceinline__ void philox_w01(uint32_t x0, uint32_t x1, uint32_t x2
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
-  w0 = x0;
-  w1 = x1;
+  return make_uint4(x0, x1, x2, x3);
+}
+
+// Output words 0 and 1 (selection and edge choice).
+__device__ __forceinline__ void philox_w01(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                           uint32_t k0, uint32_t k1, uint32_t& w0,
+                                           uint32_t& w1) {
+  const uint4 r = philox4(x0, x1, x2, x3, k0, k1);
+  w0 = r.x;
+  w1 = r.y;
 }
 
 // Sort three distinct vertex ids ascending.

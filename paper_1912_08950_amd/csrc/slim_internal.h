@@ -119,27 +119,46 @@ struct TriArgs {
   const TileRec* recs;     // graph-aligned tiles of at most tri_tile_max() entries
   uint64_t ntiles;
   uint32_t* tcount;        // Min-Count: triangles per DAG edge (NULL if unused)
-  uint32_t pass;           // 0: Min-Count counting pass, 1: selection and marks
+  uint64_t* minkey;        // Edge-Once: smallest bid per DAG edge in the current round
+  uint32_t* closed;        // Edge-Once: bitmap of closed DAG edges
+  uint64_t* eo_und;        // Edge-Once: undecided selected triangles of round r at [r]
+  uint32_t pass;           // 0: Min-Count counting, 1: selection and marks,
+                           // 2: Edge-Once bids, 3: Edge-Once acceptance
+  uint32_t round;          // Edge-Once round (1, 2, ...) of passes 2 and 3
 };
 uint64_t tri_tile_max();
-// `general` selects the instantiation that also runs Triangle p-2-Reduction
-// and both Min-Count passes; the plain one runs p-1 only.
-void triangles(const TriArgs& a, bool general, uint32_t* tile_ctr, int num_cu,
+// Instantiations of the triangle kernel: plain (p-1 only), general (also
+// p-2 and both Min-Count passes), Edge-Once (its bidding and acceptance
+// passes).
+constexpr int kModePlain = 0, kModeGeneral = 1, kModeEO = 2;
+void triangles(const TriArgs& a, int mode, uint32_t* tile_ctr, int num_cu,
                int blocks_per_cu, int chunk, hipStream_t s);
 
 // Op codes that list triangles.
 __host__ __device__ inline bool op_lists_triangles(uint32_t op) {
-  return op == SLIM_OP_TR || op == SLIM_OP_TR2 || op == SLIM_OP_MCTR;
+  return op == SLIM_OP_TR || op == SLIM_OP_TR2 || op == SLIM_OP_MCTR || op == SLIM_OP_EOTR;
 }
 __host__ __device__ inline bool op_valid(int op) {
-  return op >= SLIM_OP_TR && op <= SLIM_OP_SPECTRAL;
+  return op >= SLIM_OP_TR && op <= SLIM_OP_EOTR;
 }
+
+// Edge-Once rounds: each round clears the bids (closing, from the second
+// round on, every edge that got none) and runs the bidding and acceptance
+// passes; every launch returns at once after the round that found no
+// undecided triangle.  Rounds are enqueued Tuning::eo_rounds at a time, the
+// host checks the last round's counter in between; kEoMaxRounds bounds the
+// counter array (the rounds of greedy parallel maximal independent set with
+// random priorities grow as log of the triangle count).
+constexpr uint32_t kEoMaxRounds = 1024;
+void eo_clear_bids(uint64_t* minkey, uint32_t* closed, uint64_t m, const uint64_t* eo_und,
+                   uint32_t round, hipStream_t s);
 
 // Scheduling knobs; never change results.
 struct Tuning {
   int tri_chunk = 2048;       // out-list entries hashed per pass
   int tri_blocks_per_cu = 2;  // resident blocks of the triangle kernel per CU
   int tri_tile = 1024;        // CSR entries per triangle tile (a power of two, 256..1024)
+  int eo_rounds = 16;         // Edge-Once rounds enqueued before the host checks (1..64)
 };
 Tuning& tuning();
 // Checks a knob value; returns false if `key` is unknown or out of range.

@@ -10,6 +10,7 @@
 //   dag_rng[n]          (begin, end) of row x of the DAG, indexed by rank id
 //   eid[nnz]            for every CSR entry of a TR graph, the DAG position of its edge
 //   del[m/32]           deletion bitmap over DAG positions
+//   minkey[m], closed[m/32]  Edge-Once bids and closed edges over DAG positions
 #include "slim_internal.h"
 
 namespace slim {
@@ -39,6 +40,40 @@ void fill_u32(uint32_t* p, uint64_t len, uint32_t v, hipStream_t s) {
 
 void fill_i64(int64_t* p, uint64_t len, int64_t v, hipStream_t s) {
   if (len) hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(len)), dim3(kBlock), 0, s, p, len, v);
+}
+
+// ---------------------------------------------------- Edge-Once bids
+// Start of Edge-Once round `round`: from the second round on, an edge that
+// no undecided triangle bid on in the previous round is closed (every
+// selected triangle on it is decided); then every bid is reset.  A wave
+// takes 64 edges, so the two bitmap words of its chunk are its own.
+__global__ void k_eo_clear_bids(uint64_t* minkey, uint32_t* closed, uint64_t m,
+                                const uint64_t* eo_und, uint32_t round) {
+  if (round > 1 && eo_und[round - 1] == 0) return;  // the rounds have ended
+  const uint32_t lane = lane_id();
+  const uint64_t waves = (uint64_t)gridDim.x * kWavesPerBlock;
+  for (uint64_t c = blockIdx.x * (uint64_t)kWavesPerBlock + threadIdx.x / kWave;
+       c * kWave < m; c += waves) {
+    const uint64_t i = c * kWave + lane;
+    bool dead = false;
+    if (i < m) {
+      dead = round > 1 && minkey[i] == ~0ull;
+      minkey[i] = ~0ull;
+    }
+    const uint64_t bal = __ballot(dead);
+    if (lane == 0 && bal) {
+      closed[2 * c] |= (uint32_t)bal;
+      closed[2 * c + 1] |= (uint32_t)(bal >> 32);
+    }
+  }
+}
+
+void eo_clear_bids(uint64_t* minkey, uint32_t* closed, uint64_t m, const uint64_t* eo_und,
+                   uint32_t round, hipStream_t s) {
+  if (!m) return;
+  const uint64_t chunks = (m + kWave - 1) / kWave;
+  hipLaunchKernelGGL(k_eo_clear_bids, dim3(grid_for(chunks * kWave)), dim3(kBlock), 0, s, minkey,
+                     closed, m, eo_und, round);
 }
 
 // ------------------------------------------------------------------- scan

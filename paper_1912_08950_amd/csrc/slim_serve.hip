@@ -249,6 +249,8 @@ int run_batch(slim_server* S, Worker& W, const std::vector<Job*>& batch) {
       (void)hipGetLastError();
       run_set(P.shape, L, S->knobs, S->num_cu, ws, nullptr, nullptr, s, false);
       hipError_t e = hipGetLastError();
+      if (e == hipSuccess && eo_finish(P.shape, L, S->knobs, S->num_cu, ws, nullptr, nullptr, s))
+        e = hipErrorUnknown;
       if (e == hipSuccess)
         e = hipMemcpyAsync(W.pin_stats, dstats, sizeof(slim_stats_t) * cnt,
                            hipMemcpyDeviceToHost, s);
@@ -289,8 +291,12 @@ void worker_main(slim_server* S, int wi) {
       const double t = now_ms();
       while (!S->ready.empty() && batch.size() < S->cfg.max_batch) {
         Job* j = S->jobs[S->ready.front()].get();
+        // Edge-Once jobs batch only with each other: their per-edge arrays
+        // span the whole union, which the other jobs' reservations do not
+        // cover, and their rounds end with host checks
         if (!batch.empty() &&
-            (N + j->spec.n > 0xffffffffull || (NNZ + j->spec.nnz) / 2 > 0xffffffffull))
+            (N + j->spec.n > 0xffffffffull || (NNZ + j->spec.nnz) / 2 > 0xffffffffull ||
+             (j->spec.op == SLIM_OP_EOTR) != (batch[0]->spec.op == SLIM_OP_EOTR)))
           break;
         S->ready.pop_front();
         j->state = kRunning;

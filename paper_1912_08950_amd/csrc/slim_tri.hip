@@ -25,6 +25,20 @@
 // to each of its edges: LDS counters for (y,x) and (x,w), a global atomic
 // for (y,w)) and then marks, in each selected triangle, the edge of fewest
 // triangles (ties: the drawn index among the tied edges).
+//
+// Edge-Once p-1-Reduction (section 4.3 with the conditions of section 6.2)
+// runs in rounds of two passes over the triangles of its graphs.  Pass 2
+// (bids): every selected triangle with no closed edge writes its priority,
+// (Philox word 2, third vertex), into each of its three edges by an atomic
+// minimum.  Pass 3 (acceptance): a triangle that holds the minimum on all
+// three of its edges is considered -- it deletes its drawn edge and closes
+// all three.  Triangles that share an edge with a considered one are
+// decided against by that closed edge; an edge no undecided triangle bid on
+// is closed between rounds.  The minimum of one edge compares triangles
+// that differ only in their third vertex, so these per-edge keys order them
+// as (word 2, a, b, c) does, and the rounds reach the set that the walk in
+// that priority order reaches.  Closed in-edges are not scanned and closed
+// out-list entries are not hashed, so later rounds list fewer triangles.
 #include <type_traits>
 
 #include "slim_internal.h"
@@ -164,6 +178,7 @@ struct TriCtx {
   uint64_t thr;   // the tile's graph: selection threshold, Philox key, first vertex
   uint32_t k0, k1, vb;
   uint32_t op;    // the tile's graph's operation
+  bool eo_later;  // an Edge-Once pass after the first bids: eids are known, closed edges skipped
   uint64_t n_tri, n_sel;
 };
 
@@ -175,8 +190,13 @@ __device__ void tri_build_hash(TriCtx& C, TriSmem& S, uint32_t len, bool use_dpo
   for (int i = threadIdx.x; i < kHashCap / 32 + 2; i += kTB) S.xbits[i] = 0;
   __syncthreads();
   uint32_t* hw = reinterpret_cast<uint32_t*>(S.hb);
+  const bool skip_closed = C.eo_later;
   for (uint32_t q = threadIdx.x; q < len; q += kTB) {
     const uint32_t w = C.a.dag_col[C.D0 + q];
+    S.xold[q] = C.a.order[w];
+    // Edge-Once rounds after the first pass: a closed edge {x,w} decides
+    // every triangle on it, so it is left out of the hash
+    if (skip_closed && bit_get(C.a.closed, C.D0 + q)) continue;
     const uint32_t xb = use_dpos ? S.u.dpos[q] : 0u;
     uint32_t b = hbucket(w, xb);
     for (;;) {
@@ -190,7 +210,6 @@ __device__ void tri_build_hash(TriCtx& C, TriSmem& S, uint32_t len, bool use_dpo
       }
       b = (b + 1) & (kBuckets - 1);
     }
-    S.xold[q] = C.a.order[w];
     // counts exist only for Min-Count graphs: loaded for their selection
     // pass, zeroed for their counting pass (other operations never read them)
     if (C.X) C.X->xcnt[q] = C.a.pass == 1 && C.op == SLIM_OP_MCTR ? C.a.tcount[C.D0 + q] : 0u;
@@ -249,11 +268,19 @@ __device__ __forceinline__ void tri_mark(uint32_t* del, TriSmem& S, uint32_t exc
   }
 }
 
+// Edge-Once bid: lowers *p to key; the plain load skips the atomic when the
+// edge already holds a smaller key (values only decrease within a pass).
+__device__ __forceinline__ void eo_bid(uint64_t* p, uint64_t key) {
+  if (key < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    __hip_atomic_fetch_min(p, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Hash, select and mark the queued hits q[head .. head + cnt) (cnt <= 64);
 // one lane per hit.  Returns 1 in lanes whose triangle was selected.
-template <bool kGeneral>
+template <int kMode>
 __device__ __forceinline__ uint32_t tri_drain(const TriCtx& C, TriSmem* Sp, const uint2* q,
                                               uint32_t head, uint32_t cnt) {
+  constexpr bool kGeneral = kMode == kModeGeneral, kEO = kMode == kModeEO;
   TriSmem& S = *Sp;
   const uint32_t lane = lane_id();
   uint32_t sel = 0;
@@ -272,13 +299,37 @@ __device__ __forceinline__ uint32_t tri_drain(const TriCtx& C, TriSmem* Sp, cons
     }
     uint32_t t0 = c, t1 = u0, t2 = ow;
     sort3(t0, t1, t2);  // union ids of one graph: the order of its local ids
-    uint32_t w0, w1;
-    philox_w01(t0 - C.vb, t1 - C.vb, t2 - C.vb, 0u, C.k0, C.k1, w0, w1);
+    const uint4 wr = philox4(t0 - C.vb, t1 - C.vb, t2 - C.vb, 0u, C.k0, C.k1);
+    const uint32_t w0 = wr.x, w1 = wr.y;
+    if constexpr (kEO) {  // Edge-Once rounds
+      if ((uint64_t)w0 >= C.thr) return 0;
+      // the in-edge and the hashed entry are open in bidding passes (closed
+      // ones are neither scanned nor hashed); {y,w} is read here
+      if (C.a.pass == 2 && C.eo_later && bit_get(C.a.closed, p_yw)) return 0;
+      // per-edge keys (word 2, third vertex): {y,x} -> w, {x,w} -> y, {y,w} -> x
+      const uint64_t hi = (uint64_t)wr.z << 32;
+      const uint32_t e_yx = S.ie_e[k], e_xw = C.D0 + qpos;
+      const uint64_t k_yx = hi | (ow - C.vb), k_xw = hi | (c - C.vb), k_yw = hi | (u0 - C.vb);
+      uint64_t* mk = C.a.minkey;
+      if (C.a.pass == 2) {
+        eo_bid(mk + e_yx, k_yx);
+        eo_bid(mk + e_xw, k_xw);
+        eo_bid(mk + p_yw, k_yw);
+        return 1;  // undecided
+      }
+      if (mk[e_yx] != k_yx || mk[e_xw] != k_xw || mk[p_yw] != k_yw) return 0;
+      bit_set(C.a.closed, e_yx);
+      bit_set(C.a.closed, e_xw);
+      bit_set(C.a.closed, p_yw);
+      const uint32_t kk = __umulhi(w1, 3u);  // edge kk of ({t0,t1}, {t0,t2}, {t1,t2})
+      tri_mark(C.a.del, S, kk == 0 ? t2 : (kk == 1 ? t1 : t0), c, ow, k, qpos, C.D0, p_yw);
+      return 1;  // considered
+    }
     if ((uint64_t)w0 < C.thr) {
       sel = 1;
       // edge e of ({t0,t1}, {t0,t2}, {t1,t2}) is the one without excl[e]
       const uint32_t excl[3] = {t2, t1, t0};
-      if (!kGeneral) {
+      if constexpr (!kGeneral) {
         tri_mark(C.a.del, S, excl[__umulhi(w1, 3u)], c, ow, k, qpos, C.D0, p_yw);
       } else if (C.op == SLIM_OP_MCTR) {
         uint32_t t[3];
@@ -308,8 +359,9 @@ __device__ __forceinline__ uint32_t tri_drain(const TriCtx& C, TriSmem* Sp, cons
 }
 
 // Process the in-edges bw[b0, b1) of the tile against the current hash.
-template <bool kGeneral>
+template <int kMode>
 __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool all_rows) {
+  constexpr bool kGeneral = kMode == kModeGeneral;
   const int tid = threadIdx.x;
   const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const uint32_t lane = lane_id();
@@ -326,24 +378,32 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     const uint32_t x = C.a.rank[r];
     const uint2 yr = C.a.dag_rng[y];
     const uint32_t fs = C.a.fstart[r], fe = C.a.fstart[r + 1];
-    uint32_t lo = yr.x, hi = yr.y;
-    while (lo < hi) {
-      const uint32_t mid = lo + ((hi - lo) >> 1);
-      if (C.a.dag_col[mid] < x)
-        lo = mid + 1;
-      else
-        hi = mid;
+    uint32_t e;
+    bool closed = false;
+    if (C.eo_later) {  // found by the first Edge-Once pass
+      e = C.a.eid[j];
+      closed = bit_get(C.a.closed, e);
+    } else {
+      uint32_t lo = yr.x, hi = yr.y;
+      while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (C.a.dag_col[mid] < x)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      e = lo;  // dag_col[e] == x
+      C.a.eid[j] = e;
     }
-    const uint32_t e = lo;  // dag_col[e] == x
     // out(x) empty: no triangle, no scan (e == yr.y only for inputs that
-    // break the CSR contract: then nothing is scanned either)
-    const uint32_t beg = fe > fs && e < yr.y ? e + 1 : yr.y;
+    // break the CSR contract: then nothing is scanned either); a closed
+    // in-edge of an Edge-Once round is not scanned
+    const uint32_t beg = fe > fs && e < yr.y && !closed ? e + 1 : yr.y;
     cnt = yr.y - beg;
     xtag = all_rows ? (fs - C.D0) : 0u;
     S.ie[tid] = make_uint4(beg, x, c, r);
     S.ie_e[tid] = e;
     if (kGeneral) C.X->ie_cnt[tid] = C.a.pass == 1 && C.op == SLIM_OP_MCTR ? C.a.tcount[e] : 0u;
-    C.a.eid[j] = e;
     bmp = beg;
   }
   if ((uint32_t)tid < (kBatch + 31) / 32) S.ie_flag[tid] = 0;
@@ -454,7 +514,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
         qcnt += __popcll(bal);
         if (qcnt >= (uint32_t)kWave) {
           wave_sync();
-          C.n_sel += tri_drain<kGeneral>(C, &S, q, qhead, kWave);
+          C.n_sel += tri_drain<kMode>(C, &S, q, qhead, kWave);
           C.n_tri += 1;
           qhead = (qhead + kWave) % kQ;
           qcnt -= kWave;
@@ -464,7 +524,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
   }
   if (qcnt) {
     wave_sync();
-    C.n_sel += tri_drain<kGeneral>(C, &S, q, qhead, qcnt);
+    C.n_sel += tri_drain<kMode>(C, &S, q, qhead, qcnt);
     C.n_tri += lane < qcnt ? 1 : 0;
   }
   __syncthreads();
@@ -478,9 +538,13 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
 }
 
 // Adds the block's triangle and selection counts to graph g's counters.
+// Edge-Once bids add the undecided triangles to the round's counter (and,
+// in the first round, T and the selected count to the graph's counters);
+// acceptance passes report nothing.
 __device__ void tri_flush_counts(TriCtx& C, TriSmem& S, uint32_t g) {
   const int tid = threadIdx.x, w = tid / kWave;
   const uint64_t s0 = wave_sum64(C.n_tri), s1 = wave_sum64(C.n_sel);
+  const bool first = C.a.pass < 2 || (C.a.pass == 2 && C.a.round == 1);
   if (lane_id() == 0) {
     S.red[0][w] = s0;
     S.red[1][w] = s1;
@@ -492,8 +556,11 @@ __device__ void tri_flush_counts(TriCtx& C, TriSmem& S, uint32_t g) {
       t0 += S.red[0][i];
       t1 += S.red[1][i];
     }
-    if (t0) atomicAdd((unsigned long long*)&C.a.counters[2 * g], (unsigned long long)t0);
-    if (t1) atomicAdd((unsigned long long*)&C.a.counters[2 * g + 1], (unsigned long long)t1);
+    if (first && t0) atomicAdd((unsigned long long*)&C.a.counters[2 * g], (unsigned long long)t0);
+    if (first && t1)
+      atomicAdd((unsigned long long*)&C.a.counters[2 * g + 1], (unsigned long long)t1);
+    if (C.a.pass == 2 && t1)
+      atomicAdd((unsigned long long*)&C.a.eo_und[C.a.round], (unsigned long long)t1);
   }
   __syncthreads();
   C.n_tri = 0;
@@ -503,9 +570,10 @@ __device__ void tri_flush_counts(TriCtx& C, TriSmem& S, uint32_t g) {
 // Persistent blocks take tiles in increasing order from a counter, so the
 // graph of a block's tiles never decreases: counts are flushed when it
 // changes and at the end.
-template <bool kGeneral>
+template <int kMode>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k_triangles(
     TriArgs a, uint32_t* tile_ctr, uint32_t cap) {
+  constexpr bool kGeneral = kMode == kModeGeneral, kEO = kMode == kModeEO;
   __shared__ std::conditional_t<kGeneral, TriSmemGeneral, TriSmemPlain> SS;
   TriSmem& S = SS.s;
   TriCtx C;
@@ -520,6 +588,13 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
   C.n_sel = 0;
   C.thr = 0;
   C.k0 = C.k1 = C.vb = 0;
+  C.eo_later = kEO && !(a.pass == 2 && a.round == 1);
+  // Edge-Once rounds end once a bidding pass finds no undecided triangle:
+  // bids of round r stop if round r-1 had none, acceptance if round r has none
+  if (kEO) {
+    const uint32_t rr = a.pass == 2 ? a.round - 1 : a.round;
+    if (rr >= 1 && a.eo_und[rr] == 0) return;
+  }
   const int tid = threadIdx.x, w = tid / kWave;
   const uint32_t lane = lane_id();
   const uint64_t ntiles = a.ntiles;
@@ -533,12 +608,16 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
     const TileRec R = a.recs[t];
     if (R.span == 0) continue;  // a graph without edges
     const uint32_t gop = a.gd[R.g].op;
-    // tiles of edge-sampling graphs have no triangle work; the counting pass
-    // only visits Min-Count graphs
-    if (gop == SLIM_OP_ES || (kGeneral && a.pass == 0 && gop != SLIM_OP_MCTR)) continue;
+    // tiles of graphs that list no triangles are skipped; the counting pass
+    // visits Min-Count graphs only, the Edge-Once passes Edge-Once graphs only
+    if (!op_lists_triangles(gop)) continue;
+    if (kEO ? gop != SLIM_OP_EOTR
+            : gop == SLIM_OP_EOTR || (kGeneral && a.pass == 0 && gop != SLIM_OP_MCTR))
+      continue;
     if (R.g != gcur) {
       // the counting pass reports no triangle or selection counts
-      if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0)) tri_flush_counts(C, S, gcur);
+      if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0) && !(kEO && a.pass == 3))
+        tri_flush_counts(C, S, gcur);
       gcur = R.g;
       const GDesc& G = a.gd[gcur];
       C.thr = G.thr;
@@ -684,18 +763,19 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
       }
       C.D0 = pD0;
       tri_build_hash(C, S, plen, all_rows);
-      tri_forward_eids(C, S, pfa, pfb, all_rows);
+      if (!C.eo_later) tri_forward_eids(C, S, pfa, pfb, all_rows);
       for (uint32_t b0 = pb0; b0 < pb1; b0 += kBatch)
-        tri_batch<kGeneral>(C, S, b0, b0 + kBatch < pb1 ? b0 + kBatch : pb1, all_rows);
+        tri_batch<kMode>(C, S, b0, b0 + kBatch < pb1 ? b0 + kBatch : pb1, all_rows);
       tri_flush_xbits(C, S);
     }
   }
-  if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0)) tri_flush_counts(C, S, gcur);
+  if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0) && !(kEO && a.pass == 3))
+    tri_flush_counts(C, S, gcur);
 }
 
 uint64_t tri_tile_max() { return kTT; }
 
-void triangles(const TriArgs& a, bool general, uint32_t* tile_ctr, int num_cu,
+void triangles(const TriArgs& a, int mode, uint32_t* tile_ctr, int num_cu,
                int blocks_per_cu, int chunk, hipStream_t s) {
   uint64_t blocks = (uint64_t)num_cu * blocks_per_cu;
   if (blocks > a.ntiles) blocks = a.ntiles;
@@ -703,12 +783,15 @@ void triangles(const TriArgs& a, bool general, uint32_t* tile_ctr, int num_cu,
   fill_u32(tile_ctr, 1, 0, s);
   uint32_t cap = (uint32_t)chunk;
   if (cap > (uint32_t)kHashCap) cap = kHashCap;
-  if (general)
-    hipLaunchKernelGGL(k_triangles<true>, dim3((unsigned)blocks), dim3(kTB), 0, s, a, tile_ctr,
-                       cap);
+  if (mode == kModeGeneral)
+    hipLaunchKernelGGL(k_triangles<kModeGeneral>, dim3((unsigned)blocks), dim3(kTB), 0, s, a,
+                       tile_ctr, cap);
+  else if (mode == kModeEO)
+    hipLaunchKernelGGL(k_triangles<kModeEO>, dim3((unsigned)blocks), dim3(kTB), 0, s, a,
+                       tile_ctr, cap);
   else
-    hipLaunchKernelGGL(k_triangles<false>, dim3((unsigned)blocks), dim3(kTB), 0, s, a, tile_ctr,
-                       cap);
+    hipLaunchKernelGGL(k_triangles<kModePlain>, dim3((unsigned)blocks), dim3(kTB), 0, s, a,
+                       tile_ctr, cap);
 }
 
 }  // namespace slim

@@ -20,7 +20,7 @@ LIB_PATH = os.environ.get("SLIM_LIBRARY") or os.path.join(_HERE, "libslim.so")
 
 OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, EAGAIN = 0, -1, -2, -3, -4, -5
 VALIDATE = 1
-OP_TR, OP_ES, OP_TR2, OP_MCTR, OP_SPECTRAL = 1, 2, 3, 4, 5
+OP_TR, OP_ES, OP_TR2, OP_MCTR, OP_SPECTRAL, OP_EOTR = 1, 2, 3, 4, 5, 6
 STAT_KEYS = ("n", "m_in", "triangles", "selected", "deleted", "m_out")
 
 # Exported symbols of libslim.so, in include/slim.h order.
@@ -303,7 +303,9 @@ def edge_sample(g: Graph, p: float, seed: int, bufs: Buffers | None = None, stre
 
 
 def compress(g: Graph, op: int, p: float, seed: int, bufs: Buffers | None = None, stream=None):
-    """Enqueue any operation by op code (OP_TR, OP_ES, OP_TR2, OP_MCTR)."""
+    """Enqueue any operation by op code (OP_TR, OP_ES, OP_TR2, OP_MCTR, OP_SPECTRAL,
+    OP_EOTR).  OP_EOTR returns once its output is complete (it waits for the
+    stream)."""
     if bufs is None:
         bufs = Buffers(g, op)
     with torch.cuda.device(g.device):

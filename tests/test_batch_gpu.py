@@ -40,7 +40,8 @@ def check_batch(slim, graphs, jobs, dgs=None, oracle_idx=None, knobs=None, use_g
         if op in (slim.OP_TR, slim.OP_ES):
             want_o = oracle_run(graphs[i], "tr" if op == slim.OP_TR else "es", p, seed)
         else:
-            want_o = oracle_run_x(graphs[i], "tr2" if op == slim.OP_TR2 else "mctr", p, seed)
+            name = {slim.OP_TR2: "tr2", slim.OP_MCTR: "mctr", slim.OP_EOTR: "eotr"}[op]
+            want_o = oracle_run_x(graphs[i], name, p, seed)
         assert_same(b.result_numpy(i), want_o, f"oracle graph {i}")
     return b
 
@@ -55,15 +56,27 @@ def test_batch_of_small_graphs_mixed_ops(slim):
 
 
 def test_batch_all_operations_mixed(slim):
-    """TR, ES, TR2 and Min-Count jobs in one batch (the counting pass visits
-    only the Min-Count graphs, the general kernel serves the rest)."""
+    """TR, ES, TR2, Min-Count and Edge-Once jobs in one batch (the counting
+    pass visits only the Min-Count graphs, the Edge-Once rounds only the
+    Edge-Once graphs, the general kernel serves TR2 and Min-Count)."""
     graphs = [f() for f in SMALL.values()] + gg.batch_mix(12, 8, 1000, 6000)
-    ops = (slim.OP_TR, slim.OP_ES, slim.OP_TR2, slim.OP_MCTR)
-    jobs = [(ops[i % 4], (0.5, 1.0, 0.2, 0.8)[(i // 4) % 4], gg.mix_seed(5, i))
+    ops = (slim.OP_TR, slim.OP_ES, slim.OP_TR2, slim.OP_MCTR, slim.OP_EOTR)
+    jobs = [(ops[i % 5], (0.5, 1.0, 0.2, 0.8)[(i // 5) % 4], gg.mix_seed(5, i))
             for i in range(len(graphs))]
     check_batch(slim, graphs, jobs)
     mc_only = [(slim.OP_MCTR, 0.5, i) for i in range(len(graphs))]
     check_batch(slim, graphs, mc_only, oracle_idx=[0, 3, len(graphs) - 1])
+
+
+@pytest.mark.parametrize("use_graph,eo_rounds", [(True, 16), (True, 1), (False, 2)])
+def test_batch_edge_once(slim, use_graph, eo_rounds):
+    """Edge-Once jobs only, captured or direct, with the rounds that the
+    capture holds (eo_rounds) too few for some graphs: the rounds past them
+    run after the replay and the outputs are compacted again."""
+    graphs = gg.batch_mix(10, 13, 1000, 20000) + [gg.rmat(12, 16, 9)]
+    jobs = [(slim.OP_EOTR, (0.3, 0.6, 1.0)[i % 3], gg.mix_seed(9, i))
+            for i in range(len(graphs))]
+    check_batch(slim, graphs, jobs, knobs={"eo_rounds": eo_rounds}, use_graph=use_graph, runs=3)
 
 
 def test_batch_spectral_weights(slim):

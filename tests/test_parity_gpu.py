@@ -272,11 +272,11 @@ def test_rmat24_es_full(slim, rmat24):
 
 # ------------------------------- Triangle p-2 and Min-Count p-1 variants
 
-VARIANTS = {"tr2": 2, "mctr": 3}
+VARIANTS = {"tr2": 2, "mctr": 3, "eotr": 4}
 
 
 def gpu_run_op(slim, g, name, p, seed, validate=False):
-    op = {"tr2": slim.OP_TR2, "mctr": slim.OP_MCTR}[name]
+    op = {"tr2": slim.OP_TR2, "mctr": slim.OP_MCTR, "eotr": slim.OP_EOTR}[name]
     dg = slim.Graph.from_csr(g, validate=validate)
     return slim.result_numpy(slim.compress(dg, op, p, seed))
 
@@ -309,7 +309,8 @@ def test_variants_cfg1_and_rmat(slim, variant):
 
 
 @pytest.mark.parametrize("knobs", [{"tri_chunk": 32}, {"tri_tile": 256, "tri_blocks_per_cu": 1},
-                                   {"tri_chunk": 512, "tri_blocks_per_cu": 3}])
+                                   {"tri_chunk": 512, "tri_blocks_per_cu": 3},
+                                   {"eo_rounds": 1}, {"eo_rounds": 2, "tri_chunk": 64}])
 def test_variants_schedule_independence(slim, knobs):
     graphs = [gg.rmat(13, 16, 2), bipartite_plus_matching(3, 300), wheel(5000)]
     want = {(g.name, v): oracle_run_x(g, v, 0.6, 4) for g in graphs for v in VARIANTS}

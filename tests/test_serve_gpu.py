@@ -32,9 +32,9 @@ def test_serve_mix_equals_alone(slim):
     graphs = [f() for f in SMALL.values()] + gg.batch_mix(40, 11, 1000, 20000)
     ps = (0.2, 0.5, 0.8, 0.0, 1.0)
     jobs = []
-    ops = (slim.OP_TR, slim.OP_TR2, slim.OP_MCTR, slim.OP_ES)
+    ops = (slim.OP_TR, slim.OP_TR2, slim.OP_MCTR, slim.OP_ES, slim.OP_EOTR)
     for i, g in enumerate(graphs):
-        op = ops[i % 4] if i % 3 else slim.OP_TR
+        op = ops[i % 5] if i % 3 else slim.OP_TR
         jobs.append((g, op, ps[i % 5], gg.mix_seed(21, i), i % 2 == 0))
     want = [single(slim, g, op, p, seed) for g, op, p, seed, _ in jobs]
     dev_graphs = {i: slim.Graph.from_csr(j[0]) for i, j in enumerate(jobs) if j[4]}
