@@ -409,7 +409,8 @@ def main():
     variants = {"tr": {"ms": ms_per_step, "edges_per_s": g.m / (ms_per_step * 1e-3),
                        "stats": stats}}
     ops = [] if args.skip_variants else [("tr2", slim.OP_TR2), ("mctr", slim.OP_MCTR),
-                                          ("es", slim.OP_ES), ("spectral", slim.OP_SPECTRAL)]
+                                          ("eotr", slim.OP_EOTR), ("es", slim.OP_ES),
+                                          ("spectral", slim.OP_SPECTRAL)]
     variants["tr"]["A_S_triangles"] = triangles_of(bufs) / t_in if t_in else None
     for name, op in ops:
         vb = slim.Buffers(dg, op)

@@ -173,6 +173,7 @@ SetLayout set_layout(const SetShape& S) {
       L.minkey = c.take<uint64_t>(m);
       L.closed = c.take<uint32_t>(ceil_div(m, 32) + 1);
       L.eo_und = c.take<uint64_t>(kEoMaxRounds + 1);
+      L.eo_live = c.take<uint32_t>(S.n_tri[0]);
     }
   }
   L.scan_tmp = c.take<uint64_t>(st + 1);
@@ -250,6 +251,7 @@ void eo_rounds(const SetShape& S, const SetLayout& L, const Tuning& knobs, int n
   a.minkey = at<uint64_t>(ws, L.minkey);
   a.closed = at<uint32_t>(ws, L.closed);
   a.eo_und = at<uint64_t>(ws, L.eo_und);
+  a.eo_live = at<uint32_t>(ws, L.eo_live);
   for (uint32_t r = r0; r <= r1; ++r) {
     eo_clear_bids(a.minkey, a.closed, S.NNZ / 2, a.eo_und, r, s);
     a.round = r;
@@ -373,6 +375,7 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
       fill_u32(at<uint32_t>(ws, L.closed), ceil_div(S.NNZ / 2, 32) + 1, 0, s);
       fill_u32(reinterpret_cast<uint32_t*>(at<uint64_t>(ws, L.eo_und)), 2 * (kEoMaxRounds + 1),
                0, s);
+      fill_u32(at<uint32_t>(ws, L.eo_live), S.n_t(knobs.tri_tile), 0, s);
       eo_rounds(S, L, knobs, num_cu, ws, a, 1, (uint32_t)knobs.eo_rounds, s);
       prof_end(profile, s);
     }

@@ -122,6 +122,7 @@ struct TriArgs {
   uint64_t* minkey;        // Edge-Once: smallest bid per DAG edge in the current round
   uint32_t* closed;        // Edge-Once: bitmap of closed DAG edges
   uint64_t* eo_und;        // Edge-Once: undecided selected triangles of round r at [r]
+  uint32_t* eo_live;       // Edge-Once: last round in which each tile bid
   uint32_t pass;           // 0: Min-Count counting, 1: selection and marks,
                            // 2: Edge-Once bids, 3: Edge-Once acceptance
   uint32_t round;          // Edge-Once round (1, 2, ...) of passes 2 and 3

@@ -626,6 +626,10 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
       C.vb = (uint32_t)G.vb;
       C.op = G.op;
     }
+    // Edge-Once: a tile lists the same triangles in every pass, so one that
+    // found no undecided triangle in a bidding pass has none later either
+    if (kEO && C.eo_later && a.eo_live[t] + (a.pass == 2 ? 1u : 0u) < a.round) continue;
+    const uint64_t sel0 = C.n_sel;
     const int64_t j0 = R.j0;
     const uint32_t span = R.span;
     C.j0 = j0;
@@ -767,6 +771,13 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
       for (uint32_t b0 = pb0; b0 < pb1; b0 += kBatch)
         tri_batch<kMode>(C, S, b0, b0 + kBatch < pb1 ? b0 + kBatch : pb1, all_rows);
       tri_flush_xbits(C, S);
+    }
+    if (kEO && a.pass == 2) {  // record the round in which the tile still bid
+      if (tid == 0) S.bcast[3] = 0;
+      __syncthreads();
+      if (C.n_sel != sel0) S.bcast[3] = 1;
+      __syncthreads();
+      if (tid == 0 && S.bcast[3]) a.eo_live[t] = a.round;
     }
   }
   if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0) && !(kEO && a.pass == 3))

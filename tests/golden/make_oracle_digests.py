@@ -5,9 +5,11 @@ check bit-exact parity without rerunning a long single-threaded oracle.
 Calls only oracle/ (and the seeded input generator).  Usage:
     python tests/golden/make_oracle_digests.py [case ...]
 Cases: rmat20_tr_p0.2 rmat20_tr_p0.5 rmat20_tr_p0.8 rmat20_es_p0.5
-       rmat20_tr2_p0.5 rmat20_mctr_p0.5 rmat24_tr_p0.5 rmat24_es_p0.5 rmat24_tr2_p0.5
+       rmat20_tr2_p0.5 rmat20_mctr_p0.5 rmat20_eotr_p0.5 rmat24_tr_p0.5 rmat24_es_p0.5
+       rmat24_tr2_p0.5
 (tr: Triangle p-1-Reduction, es: uniform edge sampling, tr2: Triangle
-p-2-Reduction, mctr: Min-Count Triangle p-1-Reduction)
+p-2-Reduction, mctr: Min-Count Triangle p-1-Reduction, eotr: Edge-Once
+Triangle p-1-Reduction)
 """
 import hashlib
 import json
@@ -28,6 +30,7 @@ CASES = {
     "rmat20_es_p0.5": (20, "es", 0.5),
     "rmat20_tr2_p0.5": (20, "tr2", 0.5),
     "rmat20_mctr_p0.5": (20, "mctr", 0.5),
+    "rmat20_eotr_p0.5": (20, "eotr", 0.5),
     "rmat24_tr_p0.5": (24, "tr", 0.5),
     "rmat24_es_p0.5": (24, "es", 0.5),
     "rmat24_tr2_p0.5": (24, "tr2", 0.5),
@@ -46,7 +49,6 @@ def main(names):
     from oracle import oracle
     from paper_1912_08950_amd import graphgen
 
-    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     graphs = {}
     for name in names:
         scale, op, p = CASES[name]
@@ -54,11 +56,13 @@ def main(names):
             graphs = {scale: graphgen.rmat(scale, EDGE_FACTOR, GEN_SEED)}
         g = graphs[scale]
         t0 = time.time()
-        if op in ("tr2", "mctr"):
-            ro, col, st = oracle.triangle_reduce_x(g, p, OP_SEED, 2 if op == "tr2" else 3)
+        if op in ("tr2", "mctr", "eotr"):
+            ro, col, st = oracle.triangle_reduce_x(g, p, OP_SEED, {"tr2": 2, "mctr": 3, "eotr": 4}[op])
         else:
             fn = oracle.triangle_reduce if op == "tr" else oracle.edge_sample
             ro, col, st = fn(g, p, OP_SEED)
+        # read just before writing: other cases may have been written meanwhile
+        data = json.load(open(OUT)) if os.path.exists(OUT) else {}
         data[name] = {
             "graph": f"rmat scale={scale} edge_factor={EDGE_FACTOR} seed={GEN_SEED}",
             "graph_sha256": csr_digest(g.row_off, g.col),
