@@ -33,7 +33,8 @@ def slim(gpu):
 
 def gpu_run(slim, g, op, p, seed, validate=True):
     dg = slim.Graph.from_csr(g, validate=validate)
-    code = {"tr": slim.OP_TR, "es": slim.OP_ES, "tr2": slim.OP_TR2, "mctr": slim.OP_MCTR}[op]
+    code = {"tr": slim.OP_TR, "es": slim.OP_ES, "tr2": slim.OP_TR2, "mctr": slim.OP_MCTR,
+            "eotr": slim.OP_EOTR}[op]
     return slim.result_numpy(slim.compress(dg, code, p, seed))
 
 
@@ -234,10 +235,10 @@ def test_rmat20_tr_full(slim, rmat20, p):
     _check_sampled_rows(rmat20, ro, col, p, 1, rows)
 
 
-@pytest.mark.parametrize("variant", ["tr2", "mctr"])
+@pytest.mark.parametrize("variant", ["tr2", "mctr", "eotr"])
 def test_rmat20_variants_full(slim, rmat20, variant):
-    """R-MAT scale 20: Triangle p-2 and Min-Count p-1 Reduction against the
-    oracle's stored digests."""
+    """R-MAT scale 20: Triangle p-2, Min-Count p-1 and Edge-Once p-1
+    Reduction against the oracle's stored digests."""
     _check_digest(slim, rmat20, f"rmat20_{variant}_p0.5")
 
 
@@ -267,6 +268,12 @@ def test_rmat24_tr_full(slim, rmat24):
 
 def test_rmat24_es_full(slim, rmat24):
     _check_digest(slim, rmat24, "rmat24_es_p0.5")
+
+
+def test_rmat24_tr2_full(slim, rmat24):
+    """R-MAT scale 24: Triangle p-2-Reduction (general kernel) against the
+    oracle's stored digest."""
+    _check_digest(slim, rmat24, "rmat24_tr2_p0.5")
 
 
 
