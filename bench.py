@@ -21,6 +21,7 @@ reporting throughput and p50/p99 latency per arrival rate.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -404,6 +405,13 @@ def main():
         del ob, og
         return t
 
+    # degree-distribution Kullback-Leibler divergence of an output from the
+    # input (section 5), in bits, on the device; "inf" when the output lacks
+    # a degree that the input has
+    def degree_kl_of(bufs_out):
+        v = float(slim.degree_kl(dg.row_off, bufs_out.out_row_off).cpu().item())
+        return "inf" if math.isinf(v) else v
+
     t_in = stats["triangles"]
     ups = args.p * g.m / g.n  # upsilon = p m / n, the paper's average-degree choice
     variants = {"tr": {"ms": ms_per_step, "edges_per_s": g.m / (ms_per_step * 1e-3),
@@ -412,6 +420,7 @@ def main():
                                           ("eotr", slim.OP_EOTR), ("es", slim.OP_ES),
                                           ("spectral", slim.OP_SPECTRAL)]
     variants["tr"]["A_S_triangles"] = triangles_of(bufs) / t_in if t_in else None
+    variants["tr"]["degree_kl_bits"] = degree_kl_of(bufs)
     for name, op in ops:
         vb = slim.Buffers(dg, op)
         param = ups if op == slim.OP_SPECTRAL else args.p
@@ -427,10 +436,12 @@ def main():
         ms = e0.elapsed_time(e1) / reps
         vst = dict(zip(slim.STAT_KEYS, (int(x) for x in vb.stats.cpu().numpy())))
         variants[name] = {"ms": ms, "edges_per_s": g.m / (ms * 1e-3), "stats": vst,
-                          "A_S_triangles": triangles_of(vb) / t_in if t_in else None}
+                          "A_S_triangles": triangles_of(vb) / t_in if t_in else None,
+                          "degree_kl_bits": degree_kl_of(vb)}
         if op == slim.OP_SPECTRAL:
             variants[name]["upsilon"] = ups
-        log(f"{name}: {ms:.2f} ms {vst} A_S={variants[name]['A_S_triangles']}")
+        log(f"{name}: {ms:.2f} ms {vst} A_S={variants[name]['A_S_triangles']} "
+            f"KL={variants[name]['degree_kl_bits']}")
         del vb
     variants["triangles_per_vertex_in"] = 3 * t_in / g.n
     result["variants"] = variants

@@ -405,6 +405,30 @@ typedef struct slim_phase {
 SLIM_API int slim_profile_enable(int on);
 SLIM_API int slim_profile_read(slim_phase_t* out, int max, int* count);
 
+/* ------------------------------------------------- accuracy metrics
+ * Kullback-Leibler divergence of the degree distribution of a compressed
+ * graph from that of its input (section 5 measures information loss by
+ * D_KL(P||Q) = sum_i P(i) log2(P(i)/Q(i)), in bits): P(k) and Q(k) are the
+ * fractions of the n vertices that have degree k in the input CSR and in
+ * the compressed CSR (same n, same ids; degree = row length).  The result
+ * is >= 0, 0 iff both graphs have the same degree counts, and +infinity
+ * when some degree occurs in the input but in no vertex of the output.
+ *   d_row_off_p  device int64[n+1]: offsets of the input graph (P).
+ *   d_row_off_q  device int64[n+1]: offsets of the compressed graph (Q).
+ *   n            vertices, < 2^32 (n = 0 gives 0).
+ *   d_ws         device workspace of slim_degree_kl_workspace(n) bytes,
+ *                256-byte aligned (smaller -> SLIM_ENOMEM).
+ *   d_out        device double[1]: the divergence.
+ * The offsets are taken as given (non-decreasing from 0, as slim_load_csr
+ * requires); a row longer than n, impossible in a simple graph, counts as
+ * degree n.  Enqueued on `stream`.  The sum runs in a fixed order for a
+ * given n, so the result is reproducible bit for bit.  Errors: SLIM_EINVAL
+ * (NULL pointers, n >= 2^32), SLIM_ENOMEM, SLIM_EDEVICE.
+ */
+SLIM_API int slim_degree_kl_workspace(uint64_t n, uint64_t* bytes);
+SLIM_API int slim_degree_kl(const int64_t* d_row_off_p, const int64_t* d_row_off_q, uint64_t n,
+                            void* d_ws, uint64_t ws_bytes, double* d_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,6 +10,7 @@ path.  The readings of the paper it implements are stated in the header of
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -178,6 +179,35 @@ def tr_rows(g, p: float, seed: int, rows):
     if rc != 0:
         raise RuntimeError(f"oracle tr_rows failed rc={rc}")
     return [out_col[out_off[i]:out_off[i + 1]].copy() for i in range(len(rows))]
+
+
+def degree_distribution(row_off) -> dict:
+    """{k: fraction of the vertices with degree k} of a CSR (degree = row
+    length), in float64."""
+    deg = np.diff(np.asarray(row_off, dtype=np.int64))
+    n = deg.size
+    out = {}
+    for k, c in zip(*np.unique(deg, return_counts=True)):
+        out[int(k)] = float(c) / n
+    return out
+
+
+def degree_kl(row_off_p, row_off_q) -> float:
+    """Kullback-Leibler divergence D_KL(P||Q) = sum_k P(k) log2(P(k)/Q(k))
+    (section 5, in bits) of the degree distribution Q of a compressed graph
+    from the distribution P of its input; +inf if a degree of P is missing
+    from Q, 0 for empty graphs."""
+    if len(row_off_p) != len(row_off_q):
+        raise ValueError("both graphs must have the same vertex count")
+    if len(row_off_p) <= 1:
+        return 0.0
+    P, Q = degree_distribution(row_off_p), degree_distribution(row_off_q)
+    total = 0.0
+    for k in sorted(P):
+        if k not in Q:
+            return float("inf")
+        total += P[k] * math.log2(P[k] / Q[k])
+    return total
 
 
 def edge_triangle_counts(g) -> np.ndarray:

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libslim.so")
 SOURCES = ["slim_kernels.hip", "slim_sort.hip", "slim_tri.hip", "slim_api.hip", "slim_batch.hip",
-           "slim_serve.hip"]
+           "slim_serve.hip", "slim_metrics.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -31,7 +31,8 @@ SYMBOLS = ("slim_last_error", "slim_strerror", "slim_version", "slim_load_csr",
            "slim_serve_create", "slim_serve_submit", "slim_serve_poll", "slim_serve_wait",
            "slim_serve_next", "slim_serve_cancel", "slim_serve_copy", "slim_result_release", "slim_serve_stats",
            "slim_serve_reset_stats", "slim_serve_destroy",
-           "slim_tune_set", "slim_tune_get", "slim_profile_enable", "slim_profile_read")
+           "slim_tune_set", "slim_tune_get", "slim_profile_enable", "slim_profile_read",
+           "slim_degree_kl_workspace", "slim_degree_kl")
 
 
 class Phase(ctypes.Structure):
@@ -160,6 +161,10 @@ def _bind(path: str = LIB_PATH):
     lib.slim_profile_enable.argtypes = [i32]
     lib.slim_profile_read.restype = i32
     lib.slim_profile_read.argtypes = [ctypes.POINTER(Phase), i32, ctypes.POINTER(i32)]
+    lib.slim_degree_kl_workspace.restype = i32
+    lib.slim_degree_kl_workspace.argtypes = [u64, ctypes.POINTER(u64)]
+    lib.slim_degree_kl.restype = i32
+    lib.slim_degree_kl.argtypes = [vp, vp, u64, vp, u64, vp, vp]
     return lib
 
 
@@ -329,6 +334,28 @@ def spectral_sparsify(g: Graph, upsilon: float, seed: int, bufs: Buffers | None 
             _stream_handle(stream, g.device))
     _check(rc)
     return bufs
+
+
+def degree_kl(row_off_p, row_off_q, out=None, ws=None, stream=None):
+    """Enqueue the Kullback-Leibler divergence (bits) of the degree
+    distribution of CSR offsets ``row_off_q`` from that of ``row_off_p``
+    (device int64 tensors of n+1 entries).  Returns the device float64
+    tensor of one element that receives it."""
+    n = row_off_p.numel() - 1
+    if row_off_q.numel() != n + 1:
+        raise ValueError("both graphs must have the same vertex count")
+    dev = row_off_p.device
+    need = ctypes.c_uint64(0)
+    _check(_lib.slim_degree_kl_workspace(n, ctypes.byref(need)))
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=dev)
+    with torch.cuda.device(dev):
+        rc = _lib.slim_degree_kl(row_off_p.data_ptr(), row_off_q.data_ptr(), n, ws.data_ptr(),
+                                 ws.numel(), out.data_ptr(), _stream_handle(stream, dev))
+    _check(rc)
+    return out
 
 
 def weights_numpy(bufs: Buffers):

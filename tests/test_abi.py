@@ -46,8 +46,28 @@ def test_errors_without_gpu():
     L.slim_graph_free(None)
 
 
+def test_degree_kl_errors_without_gpu():
+    from paper_1912_08950_amd import slim
+    L = slim._lib
+    b = ctypes.c_uint64()
+    assert L.slim_degree_kl_workspace(1000, ctypes.byref(b)) == slim.OK
+    assert b.value >= 2 * 8 * 1001 and b.value % 256 == 0
+    assert L.slim_degree_kl_workspace(2**32, ctypes.byref(b)) == slim.EINVAL
+    assert L.slim_degree_kl_workspace(5, None) == slim.EINVAL
+    assert L.slim_degree_kl(1, 1, 4, None, 0, None, None) == slim.EINVAL  # d_out NULL
+    assert L.slim_degree_kl(None, 1, 4, None, 0, 8, None) == slim.EINVAL
+    assert L.slim_degree_kl(1, 1, 4, 256, 16, 8, None) == slim.ENOMEM
+
+
 def test_tuning_knobs():
     from paper_1912_08950_amd import slim
+    for k, v in (("eo_rounds", 3), ("tri_tile", 256)):
+        old = slim.tune_get(k)
+        slim.tune_set(k, v)
+        assert slim.tune_get(k) == v
+        slim.tune_set(k, old)
+    with pytest.raises(slim.SlimError):
+        slim.tune_set("eo_rounds", 0)
     old = slim.tune_get("tri_chunk")
     slim.tune_set("tri_chunk", 64)
     assert slim.tune_get("tri_chunk") == 64

@@ -1,0 +1,90 @@
+"""GPU parity of the accuracy metric (slim_degree_kl): the Kullback-Leibler
+divergence of the degree distribution of a compressed graph from that of its
+input, computed by the HIP kernels, against the oracle's float64 sum.
+
+Bar: the two sides add the same terms in different orders, each term with a
+few roundings (a quotient, log2, two products), so they may differ by about
+(K + 8) * eps * sum|terms| for K nonzero bins; +infinity and 0 must match
+exactly."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1912_08950_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def slim(gpu):
+    from paper_1912_08950_amd import slim as s
+    return s
+
+
+def gpu_kl(slim, ro_p, ro_q):
+    import torch
+    a = torch.from_numpy(np.asarray(ro_p, dtype=np.int64)).cuda()
+    b = torch.from_numpy(np.asarray(ro_q, dtype=np.int64)).cuda()
+    return float(slim.degree_kl(a, b).cpu().item())
+
+
+def assert_kl(got, ro_p, ro_q, label=""):
+    want = O.degree_kl(ro_p, ro_q)
+    if math.isinf(want) or want == 0.0:
+        assert got == want, label
+        return
+    P, Q = O.degree_distribution(ro_p), O.degree_distribution(ro_q)
+    abs_sum = sum(abs(P[k] * math.log2(P[k] / Q[k])) for k in P)
+    assert abs(got - want) <= (len(P) + 8) * EPS * abs_sum, (label, got, want)
+
+
+def compressed(slim, g, op, p, seed):
+    dg = slim.Graph.from_csr(g)
+    ro, _, _ = slim.result_numpy(slim.compress(dg, op, p, seed))
+    return ro
+
+
+@pytest.mark.parametrize("make", [lambda: gg.er(2000, 16.0, 1), lambda: gg.rmat(14, 16, 2),
+                                  lambda: gg.cycle(5000), lambda: gg.grid(40, 70)],
+                         ids=["er2000", "rmat14", "cycle5000", "grid40x70"])
+def test_degree_kl_of_compressions(slim, make):
+    g = make()
+    for op, p in ((slim.OP_TR, 0.5), (slim.OP_ES, 0.2), (slim.OP_EOTR, 0.8), (slim.OP_TR2, 0.3)):
+        ro = compressed(slim, g, op, p, 7)
+        assert_kl(gpu_kl(slim, g.row_off, ro), g.row_off, ro, f"{g.name} op={op}")
+
+
+def test_degree_kl_special_cases(slim):
+    c, pth = gg.cycle(1000), gg.path(1000)
+    assert gpu_kl(slim, c.row_off, c.row_off) == 0.0
+    assert_kl(gpu_kl(slim, c.row_off, pth.row_off), c.row_off, pth.row_off, "cycle||path")
+    assert gpu_kl(slim, pth.row_off, c.row_off) == math.inf
+    assert gpu_kl(slim, [0], [0]) == 0.0  # n = 0
+    assert gpu_kl(slim, [0, 0], [0, 0]) == 0.0  # one isolated vertex
+    # degrees above the LDS-counted range (a hub of degree 5000 losing edges)
+    star = gg.star(6000)
+    ro = compressed(slim, star, slim.OP_ES, 0.5, 3)
+    assert_kl(gpu_kl(slim, star.row_off, ro), star.row_off, ro, "star")
+
+
+def test_degree_kl_rmat20_reproducible(slim):
+    g = gg.rmat(20, 16, 1)
+    ro = compressed(slim, g, slim.OP_EOTR, 0.5, 1)
+    a, b = gpu_kl(slim, g.row_off, ro), gpu_kl(slim, g.row_off, ro)
+    assert a == b
+    assert_kl(a, g.row_off, ro, "rmat20 eotr")
+
+
+def test_degree_kl_workspace_too_small(slim):
+    import torch
+    a = torch.zeros(5, dtype=torch.int64, device="cuda")
+    with pytest.raises(ValueError):
+        slim.degree_kl(a, torch.zeros(6, dtype=torch.int64, device="cuda"))
+    ws = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    rc = slim._lib.slim_degree_kl(a.data_ptr(), a.data_ptr(), 4, ws.data_ptr(), 256,
+                                  out.data_ptr(), None)
+    assert rc == slim.ENOMEM

@@ -591,6 +591,61 @@ def test_eo_edge_count_bound_of_table_theory():
         assert np.mean([x["deleted"] for x in sts]) >= p * sts[0]["T"] / (3 * d)
 
 
+# --------------------------------------------- degree-distribution KL
+
+def test_degree_kl_closed_form():
+    """P = degrees {1, 2} half each, Q = {1: 3/4, 2: 1/4}:
+    D = 1/2 log2(2/3) + 1/2 log2(2) = 1 - log2(3)/2."""
+    p = gg.from_pairs(4, [(0, 1), (1, 2), (2, 3), (3, 0)])  # C4: all degree 2
+    p_ro = np.array([0, 1, 2, 4, 6])  # degrees 1, 1, 2, 2
+    q_ro = np.array([0, 1, 2, 3, 5])  # degrees 1, 1, 1, 2
+    assert O.degree_kl(p_ro, q_ro) == pytest.approx(1 - math.log2(3) / 2, rel=1e-15)
+    assert O.degree_kl(p.row_off, p.row_off) == 0.0
+
+
+@pytest.mark.parametrize("n", [5, 12, 1000])
+def test_degree_kl_cycle_vs_path(n):
+    """Cycle C_n (all degree 2) against the path P_n (two ends of degree 1):
+    Q(2) = (n-2)/n, so D = log2(n/(n-2)); the reverse direction is
+    infinite (degree 1 is missing from the cycle)."""
+    c, pth = gg.cycle(n), gg.path(n)
+    assert O.degree_kl(c.row_off, pth.row_off) == pytest.approx(math.log2(n / (n - 2)), rel=1e-13)
+    assert O.degree_kl(pth.row_off, c.row_off) == float("inf")
+
+
+def test_degree_kl_matches_scipy_entropy():
+    """scipy.stats.entropy(P, Q, base=2) is the same divergence."""
+    from scipy.stats import entropy
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        n = int(rng.integers(5, 300))
+        dp = rng.integers(0, 7, n)
+        dq = np.maximum(dp - rng.integers(0, 2, n), 0)
+        dq[: 7] = np.arange(7)  # every degree of P also in Q
+        ro_p = np.concatenate([[0], np.cumsum(dp)])
+        ro_q = np.concatenate([[0], np.cumsum(dq)])
+        K = max(dp.max(), dq.max()) + 1
+        P = np.bincount(dp, minlength=K) / n
+        Q = np.bincount(dq, minlength=K) / n
+        assert O.degree_kl(ro_p, ro_q) == pytest.approx(float(entropy(P, Q, base=2)), rel=1e-12,
+                                                        abs=1e-15)
+        assert O.degree_kl(ro_p, ro_q) >= 0.0  # Gibbs' inequality
+
+
+def test_degree_kl_of_sampled_cycle():
+    """Uniform sampling of the cycle C_n: P is all degree 2 and Q(2) is the
+    fraction of vertices that keep both edges, about (1-p)^2, so D is about
+    -2 log2(1-p) and grows with p (as Table `tab:pr-KL` shows for its
+    metric: p = 0.2 below p = 0.5)."""
+    g = gg.cycle(20000)
+    kl = []
+    for p in (0.2, 0.5):
+        ro, _, _ = O.edge_sample(g, p, 3)
+        kl.append(O.degree_kl(g.row_off, ro))
+        assert kl[-1] == pytest.approx(-2 * math.log2(1 - p), abs=0.05)
+    assert 0 < kl[0] < kl[1]
+
+
 # ------------------------------------------------- spectral sparsification
 
 def _pe(g, a, b, ups):
