@@ -123,6 +123,10 @@ struct TriArgs {
   uint32_t* closed;        // Edge-Once: bitmap of closed DAG edges
   uint64_t* eo_und;        // Edge-Once: undecided selected triangles of round r at [r]
   uint32_t* eo_live;       // Edge-Once: last round in which each tile bid
+  uint4* eo_list;          // Edge-Once: undecided triangles, two records each
+  uint64_t* eo_list_cnt;   // Edge-Once: records appended to eo_list
+  uint32_t* eo_state;      // Edge-Once: [0] = round that listed the triangles (0: none)
+  uint64_t eo_cap;         // Edge-Once: capacity of eo_list in triangles
   uint32_t pass;           // 0: Min-Count counting, 1: selection and marks,
                            // 2: Edge-Once bids, 3: Edge-Once acceptance
   uint32_t round;          // Edge-Once round (1, 2, ...) of passes 2 and 3
@@ -153,6 +157,9 @@ __host__ __device__ inline bool op_valid(int op) {
 constexpr uint32_t kEoMaxRounds = 1024;
 void eo_clear_bids(uint64_t* minkey, uint32_t* closed, uint64_t m, const uint64_t* eo_und,
                    uint32_t round, hipStream_t s);
+// Bids and acceptance of round a.round on the triangle list (both return at
+// once unless the list was started in an earlier round).
+void eo_list_round(const TriArgs& a, int num_cu, hipStream_t s);
 
 // Scheduling knobs; never change results.
 struct Tuning {

@@ -179,6 +179,7 @@ struct TriCtx {
   uint32_t k0, k1, vb;
   uint32_t op;    // the tile's graph's operation
   bool eo_later;  // an Edge-Once pass after the first bids: eids are known, closed edges skipped
+  bool eo_append; // an Edge-Once bidding pass that also lists the bidding triangles
   uint64_t n_tri, n_sel;
 };
 
@@ -275,12 +276,84 @@ __device__ __forceinline__ void eo_bid(uint64_t* p, uint64_t key) {
     __hip_atomic_fetch_min(p, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Edge-Once drain of the queued hits q[head .. head + cnt) (cnt <= 64): a
+// selected triangle with no closed edge bids its per-edge keys (pass 2) or,
+// if it holds the minimum on all three edges, is considered: it closes its
+// edges and marks its drawn edge (pass 3).  In the bidding pass that starts
+// the triangle list, every bidding triangle is also appended to the list
+// (one counter atomic per wave).  Returns 1 in lanes that bid / were
+// considered.
+__device__ __forceinline__ uint32_t tri_drain_eo(const TriCtx& C, TriSmem& S, const uint2* q,
+                                                 uint32_t head, uint32_t cnt) {
+  const uint32_t lane = lane_id();
+  uint32_t res = 0;
+  bool app = false;
+  uint4 ra = make_uint4(0u, 0u, 0u, 0u), rb = ra;
+  if (lane < cnt) {
+    const uint2 rec = q[(head + lane) % kQ];
+    const uint32_t k = rec.y >> 16, qpos = rec.y & 0xffffu;
+    const uint4 ie = S.ie[k];
+    const uint32_t p_yw = ie.x + (rec.x - S.ie_pre[k]);
+    const uint32_t ow = S.xold[qpos];
+    const uint32_t c = ie.z, u0 = ie.w;
+    uint32_t t0 = c, t1 = u0, t2 = ow;
+    sort3(t0, t1, t2);  // union ids of one graph: the order of its local ids
+    const uint4 wr = philox4(t0 - C.vb, t1 - C.vb, t2 - C.vb, 0u, C.k0, C.k1);
+    // the in-edge and the hashed entry are open in bidding passes (closed
+    // ones are neither scanned nor hashed); {y,w} is read here
+    const bool open = (uint64_t)wr.x < C.thr &&
+                      !(C.a.pass == 2 && C.eo_later && bit_get(C.a.closed, p_yw));
+    if (open) {
+      // per-edge keys (word 2, third vertex): {y,x} -> w, {x,w} -> y, {y,w} -> x
+      const uint64_t hi = (uint64_t)wr.z << 32;
+      const uint32_t e_yx = S.ie_e[k], e_xw = C.D0 + qpos;
+      const uint32_t lw = ow - C.vb, ly = c - C.vb, lx = u0 - C.vb;
+      const uint64_t k_yx = hi | lw, k_xw = hi | ly, k_yw = hi | lx;
+      uint64_t* mk = C.a.minkey;
+      const uint32_t kk = __umulhi(wr.y, 3u);  // edge kk of ({t0,t1}, {t0,t2}, {t1,t2})
+      const uint32_t excl = kk == 0 ? t2 : (kk == 1 ? t1 : t0);
+      if (C.a.pass == 2) {
+        eo_bid(mk + e_yx, k_yx);
+        eo_bid(mk + e_xw, k_xw);
+        eo_bid(mk + p_yw, k_yw);
+        res = 1;
+        app = true;
+        ra = make_uint4(e_yx, e_xw, p_yw, excl == ow ? e_yx : (excl == c ? e_xw : p_yw));
+        rb = make_uint4(wr.z, lw, ly, lx);
+      } else if (mk[e_yx] == k_yx && mk[e_xw] == k_xw && mk[p_yw] == k_yw) {
+        bit_set(C.a.closed, e_yx);
+        bit_set(C.a.closed, e_xw);
+        bit_set(C.a.closed, p_yw);
+        tri_mark(C.a.del, S, excl, c, ow, k, qpos, C.D0, p_yw);
+        res = 1;
+      }
+    }
+  }
+  if (C.eo_append) {  // the same in every lane of the block
+    const uint64_t mask = __ballot(app);
+    if (mask) {
+      const int leader = __builtin_ctzll(mask);
+      unsigned long long base = 0;
+      if ((int)lane == leader)
+        base = atomicAdd((unsigned long long*)C.a.eo_list_cnt, (unsigned long long)__popcll(mask));
+      base = __shfl(base, leader, kWave);
+      const uint64_t idx = base + __popcll(mask & lanemask_lt());
+      if (app && idx < C.a.eo_cap) {
+        C.a.eo_list[2 * idx] = ra;
+        C.a.eo_list[2 * idx + 1] = rb;
+      }
+    }
+  }
+  return res;
+}
+
 // Hash, select and mark the queued hits q[head .. head + cnt) (cnt <= 64);
 // one lane per hit.  Returns 1 in lanes whose triangle was selected.
 template <int kMode>
 __device__ __forceinline__ uint32_t tri_drain(const TriCtx& C, TriSmem* Sp, const uint2* q,
                                               uint32_t head, uint32_t cnt) {
   constexpr bool kGeneral = kMode == kModeGeneral, kEO = kMode == kModeEO;
+  if constexpr (kEO) return tri_drain_eo(C, *Sp, q, head, cnt);
   TriSmem& S = *Sp;
   const uint32_t lane = lane_id();
   uint32_t sel = 0;
@@ -301,30 +374,6 @@ __device__ __forceinline__ uint32_t tri_drain(const TriCtx& C, TriSmem* Sp, cons
     sort3(t0, t1, t2);  // union ids of one graph: the order of its local ids
     const uint4 wr = philox4(t0 - C.vb, t1 - C.vb, t2 - C.vb, 0u, C.k0, C.k1);
     const uint32_t w0 = wr.x, w1 = wr.y;
-    if constexpr (kEO) {  // Edge-Once rounds
-      if ((uint64_t)w0 >= C.thr) return 0;
-      // the in-edge and the hashed entry are open in bidding passes (closed
-      // ones are neither scanned nor hashed); {y,w} is read here
-      if (C.a.pass == 2 && C.eo_later && bit_get(C.a.closed, p_yw)) return 0;
-      // per-edge keys (word 2, third vertex): {y,x} -> w, {x,w} -> y, {y,w} -> x
-      const uint64_t hi = (uint64_t)wr.z << 32;
-      const uint32_t e_yx = S.ie_e[k], e_xw = C.D0 + qpos;
-      const uint64_t k_yx = hi | (ow - C.vb), k_xw = hi | (c - C.vb), k_yw = hi | (u0 - C.vb);
-      uint64_t* mk = C.a.minkey;
-      if (C.a.pass == 2) {
-        eo_bid(mk + e_yx, k_yx);
-        eo_bid(mk + e_xw, k_xw);
-        eo_bid(mk + p_yw, k_yw);
-        return 1;  // undecided
-      }
-      if (mk[e_yx] != k_yx || mk[e_xw] != k_xw || mk[p_yw] != k_yw) return 0;
-      bit_set(C.a.closed, e_yx);
-      bit_set(C.a.closed, e_xw);
-      bit_set(C.a.closed, p_yw);
-      const uint32_t kk = __umulhi(w1, 3u);  // edge kk of ({t0,t1}, {t0,t2}, {t1,t2})
-      tri_mark(C.a.del, S, kk == 0 ? t2 : (kk == 1 ? t1 : t0), c, ow, k, qpos, C.D0, p_yw);
-      return 1;  // considered
-    }
     if ((uint64_t)w0 < C.thr) {
       sel = 1;
       // edge e of ({t0,t1}, {t0,t2}, {t1,t2}) is the one without excl[e]
@@ -589,11 +638,19 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
   C.thr = 0;
   C.k0 = C.k1 = C.vb = 0;
   C.eo_later = kEO && !(a.pass == 2 && a.round == 1);
+  C.eo_append = false;
   // Edge-Once rounds end once a bidding pass finds no undecided triangle:
-  // bids of round r stop if round r-1 had none, acceptance if round r has none
+  // bids of round r stop if round r-1 had none, acceptance if round r has
+  // none.  Once the undecided triangles fit the list (round r-1 had at most
+  // its capacity), the bidding pass of round r also lists them, and later
+  // rounds run on the list instead of listing triangles again.
   if (kEO) {
     const uint32_t rr = a.pass == 2 ? a.round - 1 : a.round;
     if (rr >= 1 && a.eo_und[rr] == 0) return;
+    const uint32_t listed = a.eo_state[0];
+    if (listed != 0 && listed < a.round) return;
+    C.eo_append = a.pass == 2 && a.round >= 2 && a.eo_und[a.round - 1] <= a.eo_cap;
+    if (C.eo_append && threadIdx.x == 0) a.eo_state[0] = a.round;
   }
   const int tid = threadIdx.x, w = tid / kWave;
   const uint32_t lane = lane_id();
@@ -782,6 +839,75 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
   if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0) && !(kEO && a.pass == 3))
     tri_flush_counts(C, S, gcur);
+}
+
+// ---- Edge-Once rounds on the triangle list: records {e_yx, e_xw, e_yw,
+// e_del} {word 2, third vertex of each of the three edges}; a record whose
+// triangle is decided gets e_yx = kDead.
+constexpr uint32_t kDead = 0xffffffffu;
+constexpr int kListBlock = 256;
+
+__device__ __forceinline__ bool eo_listed_round(const TriArgs& a) {
+  const uint32_t listed = a.eo_state[0];
+  return listed != 0 && listed < a.round;
+}
+
+__global__ __launch_bounds__(kListBlock) void k_eo_list_bid(TriArgs a) {
+  if (!eo_listed_round(a) || a.eo_und[a.round - 1] == 0) return;
+  __shared__ uint64_t red[kListBlock / kWave];
+  uint64_t n = *a.eo_list_cnt;
+  if (n > a.eo_cap) n = a.eo_cap;
+  uint64_t und = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)kListBlock + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kListBlock) {
+    const uint4 r0 = a.eo_list[2 * i];
+    if (r0.x == kDead) continue;
+    if (bit_get(a.closed, r0.x) || bit_get(a.closed, r0.y) || bit_get(a.closed, r0.z)) {
+      reinterpret_cast<uint32_t*>(a.eo_list + 2 * i)[0] = kDead;
+      continue;
+    }
+    const uint4 r1 = a.eo_list[2 * i + 1];
+    const uint64_t hi = (uint64_t)r1.x << 32;
+    eo_bid(a.minkey + r0.x, hi | r1.y);
+    eo_bid(a.minkey + r0.y, hi | r1.z);
+    eo_bid(a.minkey + r0.z, hi | r1.w);
+    ++und;
+  }
+  const uint64_t t = wave_sum64(und);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t s = 0;
+    for (int i = 0; i < kListBlock / kWave; ++i) s += red[i];
+    if (s) atomicAdd((unsigned long long*)&a.eo_und[a.round], (unsigned long long)s);
+  }
+}
+
+__global__ __launch_bounds__(kListBlock) void k_eo_list_accept(TriArgs a) {
+  if (!eo_listed_round(a) || a.eo_und[a.round] == 0) return;
+  uint64_t n = *a.eo_list_cnt;
+  if (n > a.eo_cap) n = a.eo_cap;
+  for (uint64_t i = blockIdx.x * (uint64_t)kListBlock + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kListBlock) {
+    const uint4 r0 = a.eo_list[2 * i];
+    if (r0.x == kDead) continue;
+    const uint4 r1 = a.eo_list[2 * i + 1];
+    const uint64_t hi = (uint64_t)r1.x << 32;
+    if (a.minkey[r0.x] != (hi | r1.y) || a.minkey[r0.y] != (hi | r1.z) ||
+        a.minkey[r0.z] != (hi | r1.w))
+      continue;
+    bit_set(a.closed, r0.x);
+    bit_set(a.closed, r0.y);
+    bit_set(a.closed, r0.z);
+    bit_set(a.del, r0.w);
+    reinterpret_cast<uint32_t*>(a.eo_list + 2 * i)[0] = kDead;
+  }
+}
+
+void eo_list_round(const TriArgs& a, int num_cu, hipStream_t s) {
+  const unsigned blocks = (unsigned)(num_cu > 0 ? num_cu * 8 : 2048);
+  hipLaunchKernelGGL(k_eo_list_bid, dim3(blocks), dim3(kListBlock), 0, s, a);
+  hipLaunchKernelGGL(k_eo_list_accept, dim3(blocks), dim3(kListBlock), 0, s, a);
 }
 
 uint64_t tri_tile_max() { return kTT; }
