@@ -39,6 +39,10 @@
 // as (word 2, a, b, c) does, and the rounds reach the set that the walk in
 // that priority order reaches.  Closed in-edges are not scanned and closed
 // out-list entries are not hashed, so later rounds list fewer triangles.
+// Once the undecided triangles fit a list of one record per edge, the
+// bidding pass that finds them appends them, and the acceptance and all
+// later rounds run over the list (two small kernels) instead of listing
+// triangles again.
 #include <type_traits>
 
 #include "slim_internal.h"
@@ -647,8 +651,9 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
   if (kEO) {
     const uint32_t rr = a.pass == 2 ? a.round - 1 : a.round;
     if (rr >= 1 && a.eo_und[rr] == 0) return;
+    // the listing round's acceptance already runs on the list
     const uint32_t listed = a.eo_state[0];
-    if (listed != 0 && listed < a.round) return;
+    if (listed != 0 && (listed < a.round || (a.pass == 3 && listed == a.round))) return;
     C.eo_append = a.pass == 2 && a.round >= 2 && a.eo_und[a.round - 1] <= a.eo_cap;
     if (C.eo_append && threadIdx.x == 0) a.eo_state[0] = a.round;
   }
@@ -847,13 +852,15 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
 constexpr uint32_t kDead = 0xffffffffu;
 constexpr int kListBlock = 256;
 
-__device__ __forceinline__ bool eo_listed_round(const TriArgs& a) {
+// Bids on the list start the round after the listing round, acceptance on
+// the list in the listing round itself.
+__device__ __forceinline__ bool eo_listed_round(const TriArgs& a, bool accept) {
   const uint32_t listed = a.eo_state[0];
-  return listed != 0 && listed < a.round;
+  return listed != 0 && (listed < a.round || (accept && listed == a.round));
 }
 
 __global__ __launch_bounds__(kListBlock) void k_eo_list_bid(TriArgs a) {
-  if (!eo_listed_round(a) || a.eo_und[a.round - 1] == 0) return;
+  if (!eo_listed_round(a, false) || a.eo_und[a.round - 1] == 0) return;
   __shared__ uint64_t red[kListBlock / kWave];
   uint64_t n = *a.eo_list_cnt;
   if (n > a.eo_cap) n = a.eo_cap;
@@ -884,7 +891,7 @@ __global__ __launch_bounds__(kListBlock) void k_eo_list_bid(TriArgs a) {
 }
 
 __global__ __launch_bounds__(kListBlock) void k_eo_list_accept(TriArgs a) {
-  if (!eo_listed_round(a) || a.eo_und[a.round] == 0) return;
+  if (!eo_listed_round(a, true) || a.eo_und[a.round] == 0) return;
   uint64_t n = *a.eo_list_cnt;
   if (n > a.eo_cap) n = a.eo_cap;
   for (uint64_t i = blockIdx.x * (uint64_t)kListBlock + threadIdx.x; i < n;
