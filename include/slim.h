@@ -429,6 +429,42 @@ SLIM_API int slim_degree_kl_workspace(uint64_t n, uint64_t* bytes);
 SLIM_API int slim_degree_kl(const int64_t* d_row_off_p, const int64_t* d_row_off_q, uint64_t n,
                             void* d_ws, uint64_t ws_bytes, double* d_out, void* stream);
 
+/*
+ * PageRank (Table `tab:problems`; Table `tab:pr-KL` compares the PageRank
+ * distributions of original and compressed graphs): x = 1/n, then `iters`
+ * Jacobi steps x'(v) = (1-d)/n + d * sum over neighbours u of x(u)/deg(u).
+ * A vertex without edges passes nothing on (its share is not spread over
+ * the graph), so the scores sum to at most 1.
+ *   d_row_off, d_col  device CSR of the graph (n+1 offsets, columns).
+ *   n         vertices, < 2^32 (n = 0: nothing to do).
+ *   damping   d in [0, 1] (NaN or outside -> SLIM_EINVAL); 0.85 is usual.
+ *   iters     number of steps (0 leaves x = 1/n).
+ *   d_ws      device workspace of slim_pagerank_workspace(n) bytes,
+ *             256-byte aligned (smaller -> SLIM_ENOMEM).
+ *   d_pr      device double[n]: the scores.
+ * Enqueued on `stream`; every sum runs in a fixed order, so the scores are
+ * reproducible bit for bit.  Errors: SLIM_EINVAL, SLIM_ENOMEM, SLIM_EDEVICE.
+ */
+SLIM_API int slim_pagerank_workspace(uint64_t n, uint64_t* bytes);
+SLIM_API int slim_pagerank(const int64_t* d_row_off, const uint32_t* d_col, uint64_t n,
+                           double damping, uint32_t iters, void* d_ws, uint64_t ws_bytes,
+                           double* d_pr, void* stream);
+
+/*
+ * Kullback-Leibler divergence D_KL(P||Q) = sum_i P(i) log2(P(i)/Q(i)) in
+ * bits (section 5) of two non-negative device vectors of n doubles, each
+ * normalised to sum 1 (P = p / sum p, Q = q / sum q); +infinity when some
+ * q_i = 0 < p_i.  Used on PageRank scores of a graph and its compression.
+ *   d_ws   device workspace of slim_kl_divergence_workspace(n) bytes,
+ *          256-byte aligned.
+ *   d_out  device double[1].
+ * Enqueued on `stream`, fixed summation order.  Errors: SLIM_EINVAL
+ * (NULL pointers), SLIM_ENOMEM, SLIM_EDEVICE.
+ */
+SLIM_API int slim_kl_divergence_workspace(uint64_t n, uint64_t* bytes);
+SLIM_API int slim_kl_divergence(const double* d_p, const double* d_q, uint64_t n, void* d_ws,
+                                uint64_t ws_bytes, double* d_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif
