@@ -32,13 +32,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
+# the sources the triangle kernel is compiled from
+TRI_SOURCES = ("paper_1912_08950_amd/csrc/slim_tri.hip", "paper_1912_08950_amd/csrc/slim_internal.h",
+               "paper_1912_08950_amd/csrc/slim_device.h", "include/slim.h")
+
+
 def kernel_source_hash():
-    """Digest of the HIP sources, to tell whether stored counters still apply."""
+    """Digest of the triangle kernel's sources, to tell whether stored
+    counters still apply."""
     import hashlib
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1912_08950_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
+    for name in TRI_SOURCES:
+        with open(os.path.join(ROOT, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()
 
