@@ -1,7 +1,10 @@
 """CPU oracle (TEST INFRASTRUCTURE ONLY) -- ctypes front end of liboracle.so.
 
 Plain single-threaded reference for Triangle p-1-Reduction (Slim Graph,
-section 4.3) and uniform edge sampling (section 4.2.2).  Only tests/,
+section 4.3), its p-2, Min-Count and Edge-Once variants, uniform edge
+sampling (section 4.2.2), spectral sparsification (section 4.2.1) and the
+accuracy metrics of section 5 (degree-distribution and PageRank KL
+divergence, in numpy).  Only tests/,
 ``__graft_entry__.smoke()`` and bench.py's ``cpu_baseline`` leg may import
 this module; the product path never does.  It shares no code with the GPU
 path.  The readings of the paper it implements are stated in the header of

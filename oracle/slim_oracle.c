@@ -1,10 +1,10 @@
 /*
  * CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
  *
- * A plain, single-threaded, obviously-correct C reference for the two
- * compression kernels of Slim Graph (Besta et al., "Slim Graph: Practical
- * Lossy Graph Compression for Approximate Graph Processing, Storage, and
- * Analytics", SC'19):
+ * A plain, single-threaded, obviously-correct C reference for compression
+ * kernels of Slim Graph (Besta et al., "Slim Graph: Practical Lossy Graph
+ * Compression for Approximate Graph Processing, Storage, and Analytics",
+ * SC'19):
  *
  *   - Triangle p-1-Reduction (section 4.3, kernel `p-1-reduction` of the
  *     kernel listing `lst:kernels`): every triangle of the input graph is
@@ -12,6 +12,8 @@
  *     deletes one of its three edges chosen uniformly at random.
  *   - Uniform edge sampling (section 4.2.2, kernel `random_uniform`): every
  *     edge is deleted independently with probability p.
+ *   - The Triangle p-2, Min-Count and Edge-Once variants (section 4.3) and
+ *     spectral sparsification (section 4.2.1), below.
  *
  * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
  * may load this library.  It shares no code with the GPU path (its own
