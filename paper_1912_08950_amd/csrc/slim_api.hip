@@ -258,15 +258,14 @@ void eo_rounds(const SetShape& S, const SetLayout& L, const Tuning& knobs, int n
   a.eo_list_cnt = at<uint64_t>(ws, L.eo_misc);
   a.eo_state = reinterpret_cast<uint32_t*>(at<uint64_t>(ws, L.eo_misc) + 1);
   a.eo_cap = S.NNZ / 2;
+  a.gcount = S.count;
   for (uint32_t r = r0; r <= r1; ++r) {
     eo_clear_bids(a.minkey, a.closed, S.NNZ / 2, a.eo_und, r, s);
     a.round = r;
     a.pass = 2;
     triangles(a, kModeEO, at<uint32_t>(ws, L.tri_ctr), num_cu, knobs.tri_blocks_per_cu,
               knobs.tri_chunk, s);
-    a.pass = 3;
-    triangles(a, kModeEO, at<uint32_t>(ws, L.tri_ctr), num_cu, knobs.tri_blocks_per_cu,
-              knobs.tri_chunk, s);
+    eo_accept_edges(a, S.N, num_cu, s);
     eo_list_round(a, num_cu, s);
   }
 }

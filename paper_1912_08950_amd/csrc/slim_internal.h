@@ -127,9 +127,10 @@ struct TriArgs {
   uint64_t* eo_list_cnt;   // Edge-Once: records appended to eo_list
   uint32_t* eo_state;      // Edge-Once: [0] = round that listed the triangles (0: none)
   uint64_t eo_cap;         // Edge-Once: capacity of eo_list in triangles
+  uint32_t gcount;         // graphs of the set (gd[0 .. gcount))
   uint32_t pass;           // 0: Min-Count counting, 1: selection and marks,
-                           // 2: Edge-Once bids, 3: Edge-Once acceptance
-  uint32_t round;          // Edge-Once round (1, 2, ...) of passes 2 and 3
+                           // 2: Edge-Once bids
+  uint32_t round;          // Edge-Once round (1, 2, ...)
 };
 uint64_t tri_tile_max();
 // Instantiations of the triangle kernel: plain (p-1 only), general (also
@@ -157,8 +158,12 @@ __host__ __device__ inline bool op_valid(int op) {
 constexpr uint32_t kEoMaxRounds = 1024;
 void eo_clear_bids(uint64_t* minkey, uint32_t* closed, uint64_t m, const uint64_t* eo_und,
                    uint32_t round, hipStream_t s);
+// Acceptance of round a.round by an edge-parallel kernel over the n union
+// vertices (returns at once once the triangles are listed).
+void eo_accept_edges(const TriArgs& a, uint64_t n, int num_cu, hipStream_t s);
 // Bids and acceptance of round a.round on the triangle list (both return at
-// once unless the list was started in an earlier round).
+// once unless the list was started in an earlier round; acceptance also in
+// the listing round).
 void eo_list_round(const TriArgs& a, int num_cu, hipStream_t s);
 
 // Scheduling knobs; never change results.

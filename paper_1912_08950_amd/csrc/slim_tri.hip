@@ -27,12 +27,13 @@
 // triangles (ties: the drawn index among the tied edges).
 //
 // Edge-Once p-1-Reduction (section 4.3 with the conditions of section 6.2)
-// runs in rounds of two passes over the triangles of its graphs.  Pass 2
-// (bids): every selected triangle with no closed edge writes its priority,
-// (Philox word 2, third vertex), into each of its three edges by an atomic
-// minimum.  Pass 3 (acceptance): a triangle that holds the minimum on all
-// three of its edges is considered -- it deletes its drawn edge and closes
-// all three.  Triangles that share an edge with a considered one are
+// runs in rounds.  Bids (pass 2 of this kernel): every selected triangle
+// with no closed edge writes its priority, (Philox word 2, third vertex),
+// into each of its three edges by an atomic minimum.  Acceptance (an
+// edge-parallel kernel, no listing): the key on an edge names its holder
+// triangle through the third vertex, and a triangle that holds the minimum
+// on all three of its edges is considered -- it deletes its drawn edge and
+// closes all three.  Triangles that share an edge with a considered one are
 // decided against by that closed edge; an edge no undecided triangle bid on
 // is closed between rounds.  The minimum of one edge compares triangles
 // that differ only in their third vertex, so these per-edge keys order them
@@ -40,9 +41,8 @@
 // that priority order reaches.  Closed in-edges are not scanned and closed
 // out-list entries are not hashed, so later rounds list fewer triangles.
 // Once the undecided triangles fit a list of one record per edge, the
-// bidding pass that finds them appends them, and the acceptance and all
-// later rounds run over the list (two small kernels) instead of listing
-// triangles again.
+// bidding pass that finds them appends them, and all later rounds run over
+// the list (two small kernels) instead of listing triangles again.
 #include <type_traits>
 
 #include "slim_internal.h"
@@ -281,12 +281,10 @@ __device__ __forceinline__ void eo_bid(uint64_t* p, uint64_t key) {
 }
 
 // Edge-Once drain of the queued hits q[head .. head + cnt) (cnt <= 64): a
-// selected triangle with no closed edge bids its per-edge keys (pass 2) or,
-// if it holds the minimum on all three edges, is considered: it closes its
-// edges and marks its drawn edge (pass 3).  In the bidding pass that starts
-// the triangle list, every bidding triangle is also appended to the list
-// (one counter atomic per wave).  Returns 1 in lanes that bid / were
-// considered.
+// selected triangle with no closed edge bids its per-edge keys.  In the
+// bidding pass that starts the triangle list, every bidding triangle is
+// also appended to the list (one counter atomic per wave).  Returns 1 in
+// lanes that bid.
 __device__ __forceinline__ uint32_t tri_drain_eo(const TriCtx& C, TriSmem& S, const uint2* q,
                                                  uint32_t head, uint32_t cnt) {
   const uint32_t lane = lane_id();
@@ -303,10 +301,9 @@ __device__ __forceinline__ uint32_t tri_drain_eo(const TriCtx& C, TriSmem& S, co
     uint32_t t0 = c, t1 = u0, t2 = ow;
     sort3(t0, t1, t2);  // union ids of one graph: the order of its local ids
     const uint4 wr = philox4(t0 - C.vb, t1 - C.vb, t2 - C.vb, 0u, C.k0, C.k1);
-    // the in-edge and the hashed entry are open in bidding passes (closed
-    // ones are neither scanned nor hashed); {y,w} is read here
-    const bool open = (uint64_t)wr.x < C.thr &&
-                      !(C.a.pass == 2 && C.eo_later && bit_get(C.a.closed, p_yw));
+    // the in-edge and the hashed entry are open (closed ones are neither
+    // scanned nor hashed); {y,w} is read here
+    const bool open = (uint64_t)wr.x < C.thr && !(C.eo_later && bit_get(C.a.closed, p_yw));
     if (open) {
       // per-edge keys (word 2, third vertex): {y,x} -> w, {x,w} -> y, {y,w} -> x
       const uint64_t hi = (uint64_t)wr.z << 32;
@@ -316,21 +313,13 @@ __device__ __forceinline__ uint32_t tri_drain_eo(const TriCtx& C, TriSmem& S, co
       uint64_t* mk = C.a.minkey;
       const uint32_t kk = __umulhi(wr.y, 3u);  // edge kk of ({t0,t1}, {t0,t2}, {t1,t2})
       const uint32_t excl = kk == 0 ? t2 : (kk == 1 ? t1 : t0);
-      if (C.a.pass == 2) {
-        eo_bid(mk + e_yx, k_yx);
-        eo_bid(mk + e_xw, k_xw);
-        eo_bid(mk + p_yw, k_yw);
-        res = 1;
-        app = true;
-        ra = make_uint4(e_yx, e_xw, p_yw, excl == ow ? e_yx : (excl == c ? e_xw : p_yw));
-        rb = make_uint4(wr.z, lw, ly, lx);
-      } else if (mk[e_yx] == k_yx && mk[e_xw] == k_xw && mk[p_yw] == k_yw) {
-        bit_set(C.a.closed, e_yx);
-        bit_set(C.a.closed, e_xw);
-        bit_set(C.a.closed, p_yw);
-        tri_mark(C.a.del, S, excl, c, ow, k, qpos, C.D0, p_yw);
-        res = 1;
-      }
+      eo_bid(mk + e_yx, k_yx);
+      eo_bid(mk + e_xw, k_xw);
+      eo_bid(mk + p_yw, k_yw);
+      res = 1;
+      app = true;
+      ra = make_uint4(e_yx, e_xw, p_yw, excl == ow ? e_yx : (excl == c ? e_xw : p_yw));
+      rb = make_uint4(wr.z, lw, ly, lx);
     }
   }
   if (C.eo_append) {  // the same in every lane of the block
@@ -641,7 +630,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
   C.n_sel = 0;
   C.thr = 0;
   C.k0 = C.k1 = C.vb = 0;
-  C.eo_later = kEO && !(a.pass == 2 && a.round == 1);
+  C.eo_later = kEO && a.round > 1;
   C.eo_append = false;
   // Edge-Once rounds end once a bidding pass finds no undecided triangle:
   // bids of round r stop if round r-1 had none, acceptance if round r has
@@ -649,12 +638,10 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
   // its capacity), the bidding pass of round r also lists them, and later
   // rounds run on the list instead of listing triangles again.
   if (kEO) {
-    const uint32_t rr = a.pass == 2 ? a.round - 1 : a.round;
-    if (rr >= 1 && a.eo_und[rr] == 0) return;
-    // the listing round's acceptance already runs on the list
+    if (a.round > 1 && a.eo_und[a.round - 1] == 0) return;
     const uint32_t listed = a.eo_state[0];
-    if (listed != 0 && (listed < a.round || (a.pass == 3 && listed == a.round))) return;
-    C.eo_append = a.pass == 2 && a.round >= 2 && a.eo_und[a.round - 1] <= a.eo_cap;
+    if (listed != 0 && listed < a.round) return;
+    C.eo_append = a.round >= 2 && a.eo_und[a.round - 1] <= a.eo_cap;
     if (C.eo_append && threadIdx.x == 0) a.eo_state[0] = a.round;
   }
   const int tid = threadIdx.x, w = tid / kWave;
@@ -678,8 +665,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
       continue;
     if (R.g != gcur) {
       // the counting pass reports no triangle or selection counts
-      if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0) && !(kEO && a.pass == 3))
-        tri_flush_counts(C, S, gcur);
+      if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0)) tri_flush_counts(C, S, gcur);
       gcur = R.g;
       const GDesc& G = a.gd[gcur];
       C.thr = G.thr;
@@ -690,7 +676,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
     // Edge-Once: a tile lists the same triangles in every pass, so one that
     // found no undecided triangle in a bidding pass has none later either
-    if (kEO && C.eo_later && a.eo_live[t] + (a.pass == 2 ? 1u : 0u) < a.round) continue;
+    if (kEO && C.eo_later && a.eo_live[t] + 1u < a.round) continue;
     const uint64_t sel0 = C.n_sel;
     const int64_t j0 = R.j0;
     const uint32_t span = R.span;
@@ -834,7 +820,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
         tri_batch<kMode>(C, S, b0, b0 + kBatch < pb1 ? b0 + kBatch : pb1, all_rows);
       tri_flush_xbits(C, S);
     }
-    if (kEO && a.pass == 2) {  // record the round in which the tile still bid
+    if (kEO) {  // record the round in which the tile still bid
       if (tid == 0) S.bcast[3] = 0;
       __syncthreads();
       if (C.n_sel != sel0) S.bcast[3] = 1;
@@ -842,8 +828,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
       if (tid == 0 && S.bcast[3]) a.eo_live[t] = a.round;
     }
   }
-  if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0) && !(kEO && a.pass == 3))
-    tri_flush_counts(C, S, gcur);
+  if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0)) tri_flush_counts(C, S, gcur);
 }
 
 // ---- Edge-Once rounds on the triangle list: records {e_yx, e_xw, e_yw,
@@ -909,6 +894,77 @@ __global__ __launch_bounds__(kListBlock) void k_eo_list_accept(TriArgs a) {
     bit_set(a.del, r0.w);
     reinterpret_cast<uint32_t*>(a.eo_list + 2 * i)[0] = kDead;
   }
+}
+
+// Acceptance of an Edge-Once round without a list: the key on DAG edge
+// {a,b} (a's row) names its holder triangle {a,b,w} by the third vertex w.
+// The edge facing the holder's largest id checks the holder's keys on the
+// other two edges (binary searches in the DAG rows of their lower-ranked
+// ends); if it holds all three minima the triangle is considered: its three
+// edges close and its drawn edge k is marked.  Thread per union vertex.
+__device__ __forceinline__ uint32_t dag_pos(const TriArgs& a, uint32_t ru, uint32_t rv) {
+  const uint32_t lo_r = ru < rv ? ru : rv, hi_r = ru < rv ? rv : ru;
+  const uint2 rg = a.dag_rng[lo_r];
+  uint32_t lo = rg.x, hi = rg.y;
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (a.dag_col[mid] < hi_r)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo < rg.y && a.dag_col[lo] == hi_r ? lo : kDead;
+}
+
+__global__ __launch_bounds__(kListBlock) void k_eo_accept_edges(TriArgs a, uint64_t n) {
+  const uint32_t listed = a.eo_state[0];
+  if ((listed != 0 && listed <= a.round) || a.eo_und[a.round] == 0) return;
+  for (uint64_t v = blockIdx.x * (uint64_t)kListBlock + threadIdx.x; v < n;
+       v += (uint64_t)gridDim.x * kListBlock) {
+    const uint32_t p0 = a.fstart[v], p1 = a.fstart[v + 1];
+    if (p0 == p1) continue;
+    int32_t gi = -1;  // the vertex's graph, found on its first bid
+    uint32_t vb = 0;
+    for (uint32_t p = p0; p < p1; ++p) {
+      const uint64_t mk = a.minkey[p];
+      if (mk == ~0ull) continue;
+      if (gi < 0) {
+        uint32_t lo = 0, hi = a.gcount;  // last graph with vb <= v
+        while (hi - lo > 1) {
+          const uint32_t mid = lo + ((hi - lo) >> 1);
+          if (a.gd[mid].vb <= v)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        gi = (int32_t)lo;
+        vb = (uint32_t)a.gd[gi].vb;
+      }
+      const uint32_t rb = a.dag_col[p];
+      const uint32_t la = (uint32_t)v - vb, lb = a.order[rb] - vb, lw = (uint32_t)mk;
+      if (!(lw > la && lw > lb)) continue;  // the edge facing the largest id decides
+      const uint64_t hi = mk & 0xffffffff00000000ull;
+      const uint32_t rw = a.rank[vb + lw];
+      const uint32_t p_aw = dag_pos(a, a.rank[v], rw), p_bw = dag_pos(a, rb, rw);
+      if (p_aw == kDead || p_bw == kDead) continue;  // only for inputs breaking the contract
+      if (a.minkey[p_aw] != (hi | lb) || a.minkey[p_bw] != (hi | la)) continue;
+      // considered: edge k of ({t0,t1}, {t0,t2}, {t1,t2}), t2 = lw the largest
+      const GDesc& G = a.gd[gi];
+      const uint32_t t0 = la < lb ? la : lb, t1 = la < lb ? lb : la;
+      const uint4 wr = philox4(t0, t1, lw, 0u, G.k0, G.k1);
+      const uint32_t kk = __umulhi(wr.y, 3u);
+      const uint32_t p_t0w = la < lb ? p_aw : p_bw, p_t1w = la < lb ? p_bw : p_aw;
+      bit_set(a.closed, p);
+      bit_set(a.closed, p_aw);
+      bit_set(a.closed, p_bw);
+      bit_set(a.del, kk == 0 ? p : (kk == 1 ? p_t0w : p_t1w));
+    }
+  }
+}
+
+void eo_accept_edges(const TriArgs& a, uint64_t n, int num_cu, hipStream_t s) {
+  const unsigned blocks = (unsigned)(num_cu > 0 ? num_cu * 8 : 2048);
+  hipLaunchKernelGGL(k_eo_accept_edges, dim3(blocks), dim3(kListBlock), 0, s, a, n);
 }
 
 void eo_list_round(const TriArgs& a, int num_cu, hipStream_t s) {
