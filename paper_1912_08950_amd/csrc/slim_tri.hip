@@ -901,7 +901,10 @@ __global__ __launch_bounds__(kListBlock) void k_eo_list_accept(TriArgs a) {
 // The edge facing the holder's largest id checks the holder's keys on the
 // other two edges (binary searches in the DAG rows of their lower-ranked
 // ends); if it holds all three minima the triangle is considered: its three
-// edges close and its drawn edge k is marked.  Thread per union vertex.
+// edges close and its drawn edge k is marked.  A wave takes 64 consecutive
+// vertices, whose DAG rows are one contiguous range: the lanes stride over
+// it (coalesced key reads) and find each position's row among the 64 row
+// starts by a search over the lanes.
 __device__ __forceinline__ uint32_t dag_pos(const TriArgs& a, uint32_t ru, uint32_t rv) {
   const uint32_t lo_r = ru < rv ? ru : rv, hi_r = ru < rv ? rv : ru;
   const uint2 rg = a.dag_rng[lo_r];
@@ -919,37 +922,46 @@ __device__ __forceinline__ uint32_t dag_pos(const TriArgs& a, uint32_t ru, uint3
 __global__ __launch_bounds__(kListBlock) void k_eo_accept_edges(TriArgs a, uint64_t n) {
   const uint32_t listed = a.eo_state[0];
   if ((listed != 0 && listed <= a.round) || a.eo_und[a.round] == 0) return;
-  for (uint64_t v = blockIdx.x * (uint64_t)kListBlock + threadIdx.x; v < n;
-       v += (uint64_t)gridDim.x * kListBlock) {
-    const uint32_t p0 = a.fstart[v], p1 = a.fstart[v + 1];
-    if (p0 == p1) continue;
-    int32_t gi = -1;  // the vertex's graph, found on its first bid
-    uint32_t vb = 0;
-    for (uint32_t p = p0; p < p1; ++p) {
+  const uint32_t lane = lane_id();
+  const uint64_t waves = (uint64_t)gridDim.x * (kListBlock / kWave);
+  for (uint64_t g = blockIdx.x * (uint64_t)(kListBlock / kWave) + threadIdx.x / kWave;
+       g * kWave < n; g += waves) {
+    const uint64_t v0 = g * kWave;
+    const uint64_t vend = v0 + kWave < n ? v0 + kWave : n;
+    const uint32_t pend = a.fstart[vend];
+    const uint32_t fs = v0 + lane < vend ? a.fstart[v0 + lane] : pend;  // row start per lane
+    const uint32_t pbeg = __shfl(fs, 0, kWave);
+    for (uint32_t base = pbeg; base < pend; base += kWave) {
+      const uint32_t p = base + lane;
+      uint32_t own = 0;  // last lane whose row starts at or before p
+#pragma unroll
+      for (uint32_t step = kWave / 2; step > 0; step >>= 1) {
+        const uint32_t cand = own + step;
+        if (__shfl(fs, (int)cand, kWave) <= p) own = cand;
+      }
+      if (p >= pend) continue;
       const uint64_t mk = a.minkey[p];
       if (mk == ~0ull) continue;
-      if (gi < 0) {
-        uint32_t lo = 0, hi = a.gcount;  // last graph with vb <= v
-        while (hi - lo > 1) {
-          const uint32_t mid = lo + ((hi - lo) >> 1);
-          if (a.gd[mid].vb <= v)
-            lo = mid;
-          else
-            hi = mid;
-        }
-        gi = (int32_t)lo;
-        vb = (uint32_t)a.gd[gi].vb;
+      const uint32_t v = (uint32_t)(v0 + own);
+      uint32_t lo = 0, hi = a.gcount;  // the vertex's graph: last with vb <= v
+      while (hi - lo > 1) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (a.gd[mid].vb <= v)
+          lo = mid;
+        else
+          hi = mid;
       }
+      const GDesc& G = a.gd[lo];
+      const uint32_t vb = (uint32_t)G.vb;
       const uint32_t rb = a.dag_col[p];
-      const uint32_t la = (uint32_t)v - vb, lb = a.order[rb] - vb, lw = (uint32_t)mk;
+      const uint32_t la = v - vb, lb = a.order[rb] - vb, lw = (uint32_t)mk;
       if (!(lw > la && lw > lb)) continue;  // the edge facing the largest id decides
-      const uint64_t hi = mk & 0xffffffff00000000ull;
+      const uint64_t hk = mk & 0xffffffff00000000ull;
       const uint32_t rw = a.rank[vb + lw];
       const uint32_t p_aw = dag_pos(a, a.rank[v], rw), p_bw = dag_pos(a, rb, rw);
       if (p_aw == kDead || p_bw == kDead) continue;  // only for inputs breaking the contract
-      if (a.minkey[p_aw] != (hi | lb) || a.minkey[p_bw] != (hi | la)) continue;
+      if (a.minkey[p_aw] != (hk | lb) || a.minkey[p_bw] != (hk | la)) continue;
       // considered: edge k of ({t0,t1}, {t0,t2}, {t1,t2}), t2 = lw the largest
-      const GDesc& G = a.gd[gi];
       const uint32_t t0 = la < lb ? la : lb, t1 = la < lb ? lb : la;
       const uint4 wr = philox4(t0, t1, lw, 0u, G.k0, G.k1);
       const uint32_t kk = __umulhi(wr.y, 3u);
