@@ -41,59 +41,136 @@ uint64_t size_class(uint64_t bytes) {
   return (bytes + step - 1) / step * step;
 }
 
-// Caching device allocator.  Freed blocks are kept by size and reused for
-// any request of at least half their size (the smallest fitting block
-// first); only when live plus cached bytes would pass `cap` are cached blocks
-// freed (hipFree waits for the device, so this is kept rare).  A block's
-// size travels with it: alloc returns it in *got, free takes it back.
+// Sub-allocating device allocator.  Device memory is taken from the runtime
+// in chunks (kChunk bytes, or one request's size if larger) and carved into
+// ranges best fit; freed ranges coalesce with their free neighbours.  In
+// steady serving no hipMalloc or hipFree is called (hipFree waits for the
+// whole device, which would stall every worker).  A chunk is returned to the
+// runtime only when it is entirely free and a new chunk would pass `cap`.
+// A range's size travels with it: alloc returns it in *got, free takes it
+// back.
 class Arena {
  public:
+  static constexpr uint64_t kChunk = uint64_t(2) << 30;
+  static constexpr uint64_t kAlignB = 4096;
   void set_cap(uint64_t cap) { cap_ = cap; }
   void* alloc(uint64_t bytes, uint64_t* got) {
-    const uint64_t c = size_class(bytes);
+    const uint64_t c = (std::max<uint64_t>(bytes, 1) + kAlignB - 1) / kAlignB * kAlignB;
     std::lock_guard<std::mutex> lk(mu_);
-    auto it = cache_.lower_bound(c);
-    if (it != cache_.end() && it->first <= 2 * c) {
-      void* p = it->second;
-      *got = it->first;
-      cached_ -= it->first;
-      live_ += it->first;
-      cache_.erase(it);
-      return p;
+    auto it = by_size_.lower_bound(c);
+    if (it == by_size_.end()) {
+      if (!grow(c)) return nullptr;
+      it = by_size_.lower_bound(c);
+      if (it == by_size_.end()) return nullptr;
     }
-    while (live_ + cached_ + c > cap_ && !cache_.empty()) {
-      auto big = std::prev(cache_.end());
-      (void)hipFree(big->second);
-      cached_ -= big->first;
-      cache_.erase(big);
-    }
-    void* p = nullptr;
-    if (hipMalloc(&p, c) != hipSuccess) {
-      (void)hipGetLastError();
-      return nullptr;
-    }
+    const Range r = it->second;
+    const uint64_t len = it->first;
+    by_size_.erase(it);
+    by_off_.erase(r);
+    if (len > c) insert_free(Range{r.chunk, r.off + c}, len - c);
+    chunks_[r.chunk].used += c;
     *got = c;
-    live_ += c;
-    return p;
+    return chunks_[r.chunk].base + r.off;
   }
   void free(void* p, uint64_t size) {
     if (!p) return;
     std::lock_guard<std::mutex> lk(mu_);
-    cache_.emplace(size, p);
-    live_ -= size;
-    cached_ += size;
+    char* q = static_cast<char*>(p);
+    auto ci = by_base_.upper_bound(q);  // the chunk holding q: last base <= q
+    if (ci == by_base_.begin()) return;
+    --ci;
+    const uint32_t k = ci->second;
+    chunks_[k].used -= size;
+    uint64_t off = (uint64_t)(q - chunks_[k].base), len = size;
+    auto nx = by_off_.lower_bound(Range{k, off});
+    if (nx != by_off_.end() && nx->first.chunk == k && nx->first.off == off + len) {
+      len += nx->second;  // merge with the next free range
+      erase_size(nx->first, nx->second);
+      nx = by_off_.erase(nx);
+    }
+    if (nx != by_off_.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first.chunk == k && pv->first.off + pv->second == off) {
+        off = pv->first.off;  // merge with the previous free range
+        len += pv->second;
+        erase_size(pv->first, pv->second);
+        by_off_.erase(pv);
+      }
+    }
+    insert_free(Range{k, off}, len);
   }
   void release_all() {
     std::lock_guard<std::mutex> lk(mu_);
-    for (auto& kv : cache_) (void)hipFree(kv.second);
-    cache_.clear();
-    cached_ = 0;
+    for (auto& ch : chunks_)
+      if (ch.base) (void)hipFree(ch.base);
+    chunks_.clear();
+    by_size_.clear();
+    by_off_.clear();
+    by_base_.clear();
+    total_ = 0;
   }
 
  private:
+  struct Range {
+    uint32_t chunk;
+    uint64_t off;
+    bool operator<(const Range& o) const {
+      return chunk != o.chunk ? chunk < o.chunk : off < o.off;
+    }
+  };
+  struct Chunk {
+    char* base = nullptr;
+    uint64_t size = 0, used = 0;
+  };
+  void insert_free(Range r, uint64_t len) {
+    by_off_.emplace(r, len);
+    by_size_.emplace(len, r);
+  }
+  void erase_size(Range r, uint64_t len) {
+    auto rg = by_size_.equal_range(len);
+    for (auto i = rg.first; i != rg.second; ++i)
+      if (i->second.chunk == r.chunk && i->second.off == r.off) {
+        by_size_.erase(i);
+        return;
+      }
+  }
+  // A new chunk for a request of c bytes; entirely free chunks go back to
+  // the runtime first if the new one would pass the cap.
+  bool grow(uint64_t c) {
+    const uint64_t sz = c > kChunk ? c : kChunk;
+    for (uint32_t k = 0; total_ + sz > cap_ && k < chunks_.size(); ++k) {
+      Chunk& ch = chunks_[k];
+      if (!ch.base || ch.used != 0) continue;
+      erase_size(Range{k, 0}, ch.size);
+      by_off_.erase(Range{k, 0});
+      by_base_.erase(ch.base);
+      (void)hipFree(ch.base);
+      total_ -= ch.size;
+      ch = Chunk{};
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, sz) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    uint32_t k = 0;
+    while (k < chunks_.size() && chunks_[k].base) ++k;  // reuse a returned slot
+    if (k == chunks_.size()) chunks_.emplace_back();
+    chunks_[k].base = static_cast<char*>(p);
+    chunks_[k].size = sz;
+    chunks_[k].used = 0;
+    by_base_.emplace(chunks_[k].base, k);
+    total_ += sz;
+    insert_free(Range{k, 0}, sz);
+    return true;
+  }
+
   std::mutex mu_;
-  std::multimap<uint64_t, void*> cache_;
-  uint64_t live_ = 0, cached_ = 0, cap_ = 0;
+  std::vector<Chunk> chunks_;
+  std::multimap<uint64_t, Range> by_size_;  // free ranges by length
+  std::map<Range, uint64_t> by_off_;        // free ranges by position
+  std::map<char*, uint32_t> by_base_;       // chunk by base address
+  uint64_t total_ = 0, cap_ = 0;
 };
 
 enum State { kQueued, kReady, kRunning, kDone };
