@@ -6,10 +6,11 @@ Calls only oracle/ (and the seeded input generator).  Usage:
     python tests/golden/make_oracle_digests.py [case ...]
 Cases: rmat20_tr_p0.2 rmat20_tr_p0.5 rmat20_tr_p0.8 rmat20_es_p0.5
        rmat20_tr2_p0.5 rmat20_mctr_p0.5 rmat20_eotr_p0.5 rmat24_tr_p0.5 rmat24_es_p0.5
-       rmat24_tr2_p0.5
+       rmat24_tr2_p0.5 rmat24_spectral_p0.5
 (tr: Triangle p-1-Reduction, es: uniform edge sampling, tr2: Triangle
 p-2-Reduction, mctr: Min-Count Triangle p-1-Reduction, eotr: Edge-Once
-Triangle p-1-Reduction)
+Triangle p-1-Reduction, spectral: spectral sparsification with upsilon =
+p m / n, the weights digested too)
 """
 import hashlib
 import json
@@ -34,6 +35,7 @@ CASES = {
     "rmat24_tr_p0.5": (24, "tr", 0.5),
     "rmat24_es_p0.5": (24, "es", 0.5),
     "rmat24_tr2_p0.5": (24, "tr2", 0.5),
+    "rmat24_spectral_p0.5": (24, "spectral", 0.5),
 }
 GEN_SEED, OP_SEED, EDGE_FACTOR = 1, 1, 16
 
@@ -56,7 +58,12 @@ def main(names):
             graphs = {scale: graphgen.rmat(scale, EDGE_FACTOR, GEN_SEED)}
         g = graphs[scale]
         t0 = time.time()
-        if op in ("tr2", "mctr", "eotr"):
+        w_sha = None
+        if op == "spectral":
+            ups = p * g.m / g.n
+            ro, col, w, st = oracle.spectral_sparsify(g, ups, OP_SEED)
+            w_sha = hashlib.sha256(np.ascontiguousarray(w, dtype="<f4").tobytes()).hexdigest()
+        elif op in ("tr2", "mctr", "eotr"):
             ro, col, st = oracle.triangle_reduce_x(g, p, OP_SEED, {"tr2": 2, "mctr": 3, "eotr": 4}[op])
         else:
             fn = oracle.triangle_reduce if op == "tr" else oracle.edge_sample
@@ -71,6 +78,9 @@ def main(names):
             "stats": st,
             "oracle_seconds": round(time.time() - t0, 1),
         }
+        if w_sha is not None:
+            data[name]["weights_sha256"] = w_sha
+            data[name]["upsilon"] = ups
         json.dump(data, open(OUT + ".tmp", "w"), indent=1, sort_keys=True)
         os.replace(OUT + ".tmp", OUT)
         print(name, data[name], flush=True)

@@ -270,6 +270,55 @@ def test_rmat24_es_full(slim, rmat24):
     _check_digest(slim, rmat24, "rmat24_es_p0.5")
 
 
+def test_rmat24_spectral_full(slim, rmat24):
+    """R-MAT scale 24: spectral sparsification with upsilon = p m / n, the
+    output CSR and every float32 weight against the oracle's stored digests."""
+    import hashlib
+    name = "rmat24_spectral_p0.5"
+    d = _digests().get(name)
+    if d is None:
+        pytest.skip(f"no stored oracle digest for {name}")
+    assert csr_digest(rmat24.row_off, rmat24.col) == d["graph_sha256"], "generator output changed"
+    ups = 0.5 * rmat24.m / rmat24.n
+    assert ups == d["upsilon"]
+    dg = slim.Graph.from_csr(rmat24)
+    bufs = slim.spectral_sparsify(dg, ups, d["seed"])
+    ro, col, st = slim.result_numpy(bufs)
+    w = slim.weights_numpy(bufs)
+    assert st["deleted"] == d["stats"]["deleted"] and st["m_out"] == d["stats"]["m_out"]
+    assert csr_digest(ro, col) == d["out_sha256"]
+    assert hashlib.sha256(np.ascontiguousarray(w, dtype="<f4").tobytes()).hexdigest() == \
+        d["weights_sha256"]
+
+
+def test_rmat24_eotr_properties(slim, rmat24):
+    """R-MAT scale 24, Edge-Once p-1 (the oracle's sort of 5e9 selected
+    triangles does not fit in host memory, so properties that hold at any
+    size): the same triangles and selections as p-1 (stored digest), at most
+    m/3 deletions, output rows are subsets of the input rows, and every
+    deleted edge of 300 sampled rows keeps a two-edge path (2-spanner)."""
+    ref = _digests().get("rmat24_tr_p0.5")
+    if ref is None:
+        pytest.skip("no stored oracle digest for rmat24_tr_p0.5")
+    ro, col, st = gpu_run(slim, rmat24, "eotr", 0.5, 1, validate=False)
+    assert st["triangles"] == ref["stats"]["T"] and st["selected"] == ref["stats"]["selected"]
+    assert st["deleted"] == st["m_in"] - st["m_out"] and 0 < st["deleted"] <= st["m_in"] // 3
+    assert ro[-1] == 2 * st["m_out"]
+    rng = np.random.default_rng(13)
+    deg = rmat24.degrees()
+    rows = rng.choice(np.flatnonzero((deg > 1) & (deg < 300)), 300, replace=False)
+    n_del = 0
+    for u in rows:
+        a = rmat24.col[rmat24.row_off[u]:rmat24.row_off[u + 1]]
+        b = col[ro[u]:ro[u + 1]]
+        assert np.all(np.diff(b.astype(np.int64)) > 0) and np.all(np.isin(b, a)), u
+        for v in np.setdiff1d(a, b):
+            n_del += 1
+            bv = col[ro[v]:ro[v + 1]]
+            assert np.intersect1d(b, bv).size > 0, (u, v)
+    assert n_del > 0
+
+
 def test_rmat24_tr2_full(slim, rmat24):
     """R-MAT scale 24: Triangle p-2-Reduction (general kernel) against the
     oracle's stored digest."""
