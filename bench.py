@@ -128,10 +128,37 @@ def cpu_baseline(scale):
     t0 = time.perf_counter()
     _, _, st = oracle.triangle_reduce(g, 0.5, 1)
     dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": g.m / dt, "unit": "input edges/s", "cores": 1, "kind": "oracle",
             "sample": f"full oracle run on R-MAT scale {scale} (edge factor 16, seed 1, "
                       f"m={g.m}, T={st['T']}), p=0.5: {dt:.1f} s",
-            "seconds": round(dt, 2)}
+            "seconds": round(dt, 2), "host_cpu": model, "host_threads": os.cpu_count()}
+
+
+def stream_copy_gbs(stream):
+    """Achievable HBM rate of a plain device copy (1 GiB read + 1 GiB written
+    per launch, best of 5), the second denominator beside the published peak."""
+    import torch
+    n = 1 << 28
+    src = torch.arange(n, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    best = None
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dst.copy_(src)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * 4 * n / (best * 1e-3) / 1e9
 
 
 def bench_batch(args, log):
@@ -366,6 +393,10 @@ def main():
 
     tri_ms = float(np.mean(phases["triangles"]))
     tri_bytes = tri_kernel_bytes(g, work)
+    copy_gbs = stream_copy_gbs(stream)
+    # per-step totals from the phase events (the paper reports means; the
+    # spread of the K steps is given beside it)
+    step_ms = [float(sum(v[i] for v in phases.values())) for i in range(args.steps)]
     achieved = tri_bytes / (tri_ms * 1e-3) / 1e9
     traffic = stored_traffic(os.path.join(ROOT, "profiles", f"k_triangles_rmat{args.scale}.txt"))
     result = {
@@ -395,7 +426,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes": tri_bytes, "kernel_ms": tri_ms,
                      "scan_items": work["sum_out_pairs"],
-                     "scan_bytes_per_s": 4 * work["sum_out_pairs"] / (tri_ms * 1e-3)},
+                     "scan_bytes_per_s": 4 * work["sum_out_pairs"] / (tri_ms * 1e-3),
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
+        "step_ms": step_ms,
+        "step_ms_min_max": [min(step_ms), max(step_ms)],
         "step_algorithmic_gbs": step_bytes(g, work, stats["m_out"]) / (ms_per_step * 1e-3) / 1e9,
     }
     # the other operations on the same graph, each timed, and the scalar
