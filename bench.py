@@ -337,7 +337,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(graphs are processed whole on one device); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
