@@ -63,6 +63,7 @@ constexpr int kQ = 128;              // per-wave hit queue (records)
 #endif
 constexpr int kUnroll = SLIM_TRI_UNROLL;  // windows of 64 items whose loads are in flight together
 constexpr uint32_t kEmpty = 0xffffffffu;
+constexpr uint32_t kDead = 0xffffffffu;  // Edge-Once list record of a decided triangle
 
 static_assert(kBatch <= kTB, "one thread per in-edge in the setup");
 static_assert(kTC <= kWave, "one wave scans the chunk sums");
@@ -184,6 +185,9 @@ struct TriCtx {
   uint32_t op;    // the tile's graph's operation
   bool eo_later;  // an Edge-Once pass after the first bids: eids are known, closed edges skipped
   bool eo_append; // an Edge-Once bidding pass that also lists the bidding triangles
+  uint64_t wcur;  // Edge-Once list slots reserved by this wave: next free one
+  uint32_t wleft; //   and how many are left (the same in every lane of the wave)
+  uint32_t achunk;  // slots a wave reserves at a time
   uint64_t n_tri, n_sel;
 };
 
@@ -285,7 +289,7 @@ __device__ __forceinline__ void eo_bid(uint64_t* p, uint64_t key) {
 // bidding pass that starts the triangle list, every bidding triangle is
 // also appended to the list (one counter atomic per wave).  Returns 1 in
 // lanes that bid.
-__device__ __forceinline__ uint32_t tri_drain_eo(const TriCtx& C, TriSmem& S, const uint2* q,
+__device__ __forceinline__ uint32_t tri_drain_eo(TriCtx& C, TriSmem& S, const uint2* q,
                                                  uint32_t head, uint32_t cnt) {
   const uint32_t lane = lane_id();
   uint32_t res = 0;
@@ -323,14 +327,26 @@ __device__ __forceinline__ uint32_t tri_drain_eo(const TriCtx& C, TriSmem& S, co
     }
   }
   if (C.eo_append) {  // the same in every lane of the block
+    // slots come from the wave's reserved run first; the rest from a new run
+    // of max(rest, achunk) slots, taken with one atomic on the list counter
     const uint64_t mask = __ballot(app);
     if (mask) {
-      const int leader = __builtin_ctzll(mask);
-      unsigned long long base = 0;
-      if ((int)lane == leader)
-        base = atomicAdd((unsigned long long*)C.a.eo_list_cnt, (unsigned long long)__popcll(mask));
-      base = __shfl(base, leader, kWave);
-      const uint64_t idx = base + __popcll(mask & lanemask_lt());
+      const uint32_t n = __popcll(mask), r = __popcll(mask & lanemask_lt());
+      const uint32_t take0 = n < C.wleft ? n : C.wleft;
+      const uint64_t base0 = C.wcur;
+      uint64_t base1 = 0;
+      if (n > take0) {
+        const uint32_t need = n - take0, run = need > C.achunk ? need : C.achunk;
+        unsigned long long nb = 0;
+        if (lane == 0) nb = atomicAdd((unsigned long long*)C.a.eo_list_cnt, (unsigned long long)run);
+        base1 = __shfl(nb, 0, kWave);
+        C.wcur = base1 + need;
+        C.wleft = run - need;
+      } else {
+        C.wcur += n;
+        C.wleft -= n;
+      }
+      const uint64_t idx = r < take0 ? base0 + r : base1 + (r - take0);
       if (app && idx < C.a.eo_cap) {
         C.a.eo_list[2 * idx] = ra;
         C.a.eo_list[2 * idx + 1] = rb;
@@ -343,7 +359,7 @@ __device__ __forceinline__ uint32_t tri_drain_eo(const TriCtx& C, TriSmem& S, co
 // Hash, select and mark the queued hits q[head .. head + cnt) (cnt <= 64);
 // one lane per hit.  Returns 1 in lanes whose triangle was selected.
 template <int kMode>
-__device__ __forceinline__ uint32_t tri_drain(const TriCtx& C, TriSmem* Sp, const uint2* q,
+__device__ __forceinline__ uint32_t tri_drain(TriCtx& C, TriSmem* Sp, const uint2* q,
                                               uint32_t head, uint32_t cnt) {
   constexpr bool kGeneral = kMode == kModeGeneral, kEO = kMode == kModeEO;
   if constexpr (kEO) return tri_drain_eo(C, *Sp, q, head, cnt);
@@ -641,7 +657,14 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (a.round > 1 && a.eo_und[a.round - 1] == 0) return;
     const uint32_t listed = a.eo_state[0];
     if (listed != 0 && listed < a.round) return;
-    C.eo_append = a.round >= 2 && a.eo_und[a.round - 1] <= a.eo_cap;
+    // every wave may leave up to achunk reserved slots unused (marked dead
+    // at the end), so listing starts only when they fit beside the triangles
+    const uint64_t waves = (uint64_t)gridDim.x * kTW;
+    const uint64_t ch = a.eo_cap / (8 * waves);
+    C.achunk = (uint32_t)(ch < 256 ? ch : 256);
+    C.wcur = 0;
+    C.wleft = 0;
+    C.eo_append = a.round >= 2 && a.eo_und[a.round - 1] + waves * C.achunk <= a.eo_cap;
     if (C.eo_append && threadIdx.x == 0) a.eo_state[0] = a.round;
   }
   const int tid = threadIdx.x, w = tid / kWave;
@@ -829,12 +852,15 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
   }
   if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0)) tri_flush_counts(C, S, gcur);
+  if (kEO && C.eo_append)  // the wave's unused reserved slots become dead records
+    for (uint32_t i = lane; i < C.wleft; i += kWave)
+      if (C.wcur + i < a.eo_cap)
+        reinterpret_cast<uint32_t*>(a.eo_list + 2 * (C.wcur + i))[0] = kDead;
 }
 
 // ---- Edge-Once rounds on the triangle list: records {e_yx, e_xw, e_yw,
 // e_del} {word 2, third vertex of each of the three edges}; a record whose
-// triangle is decided gets e_yx = kDead.
-constexpr uint32_t kDead = 0xffffffffu;
+// triangle is decided (or a reserved slot that stayed unused) gets e_yx = kDead.
 constexpr int kListBlock = 256;
 
 // Bids on the list start the round after the listing round, acceptance on
