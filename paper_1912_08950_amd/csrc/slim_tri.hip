@@ -107,6 +107,12 @@ struct TriSmemGeneral {
   TriSmem s;
   TriX x;
 };
+// LDS of the Edge-Once instantiation: the smallest bid on each in-edge of
+// the batch, written to the global minimum once per batch.
+struct TriSmemEO {
+  TriSmem s;
+  uint64_t ie_key[kBatch];
+};
 
 __device__ __forceinline__ uint32_t hbucket(uint32_t w, uint32_t xb) {
   return ((w ^ (xb * 0x85EBCA6Bu)) * 0x9E3779B1u) >> (32 - kBucketBits);
@@ -176,6 +182,7 @@ __device__ void tri_tile_rows(const int64_t* row_off, int64_t j0, uint32_t lo, u
 struct TriCtx {
   TriArgs a;
   TriX* X;        // general instantiation only
+  uint64_t* ie_key;  // Edge-Once instantiation only
   uint32_t cap;   // out-list entries hashed per pass (<= kHashCap)
   int64_t j0;
   uint32_t D0;    // first DAG position of the hashed range
@@ -317,7 +324,7 @@ __device__ __forceinline__ uint32_t tri_drain_eo(TriCtx& C, TriSmem& S, const ui
       uint64_t* mk = C.a.minkey;
       const uint32_t kk = __umulhi(wr.y, 3u);  // edge kk of ({t0,t1}, {t0,t2}, {t1,t2})
       const uint32_t excl = kk == 0 ? t2 : (kk == 1 ? t1 : t0);
-      eo_bid(mk + e_yx, k_yx);
+      atomicMin((unsigned long long*)&C.ie_key[k], (unsigned long long)k_yx);  // LDS
       eo_bid(mk + e_xw, k_xw);
       eo_bid(mk + p_yw, k_yw);
       res = 1;
@@ -465,6 +472,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     bmp = beg;
   }
   if ((uint32_t)tid < (kBatch + 31) / 32) S.ie_flag[tid] = 0;
+  if (C.ie_key && (uint32_t)tid < nin) C.ie_key[tid] = ~0ull;
   {  // block exclusive scan of cnt into ie_pre; scan records {beg - pre, tag, next start}
     const uint64_t incl = wave_incl_sum64(cnt);
     if (lane == kWave - 1) S.wsum[w] = (uint32_t)incl;
@@ -592,6 +600,8 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
   } else if ((uint32_t)tid < nin && (S.ie_flag[tid >> 5] & (1u << (tid & 31)))) {
     bit_set(C.a.del, S.ie_e[tid]);
   }
+  if (C.ie_key && (uint32_t)tid < nin && C.ie_key[tid] != ~0ull)  // the batch's {y,x} bids
+    eo_bid(C.a.minkey + S.ie_e[tid], C.ie_key[tid]);
   __syncthreads();
 }
 
@@ -632,7 +642,8 @@ template <int kMode>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k_triangles(
     TriArgs a, uint32_t* tile_ctr, uint32_t cap) {
   constexpr bool kGeneral = kMode == kModeGeneral, kEO = kMode == kModeEO;
-  __shared__ std::conditional_t<kGeneral, TriSmemGeneral, TriSmemPlain> SS;
+  __shared__ std::conditional_t<kGeneral, TriSmemGeneral,
+                                std::conditional_t<kEO, TriSmemEO, TriSmemPlain>> SS;
   TriSmem& S = SS.s;
   TriCtx C;
   C.a = a;
@@ -640,6 +651,10 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
     C.X = &SS.x;
   else
     C.X = nullptr;
+  if constexpr (kEO)
+    C.ie_key = SS.ie_key;
+  else
+    C.ie_key = nullptr;
   C.cap = cap;
   C.op = 0;
   C.n_tri = 0;
