@@ -22,8 +22,9 @@
  *
  * Readings of points the paper leaves open (each restated where it is used):
  *   R1  p in TR is the probability that a triangle is selected for
- *       reduction (section 4.3 text: "probability of sampling a triangle";
- *       Table `tab:tcv`: 0.9-1-TR leaves fewer triangles than 0.2-1-TR).
+ *       reduction (section 4.3 calls p the sampling probability of a
+ *       triangle; Table `tab:tcv`: 0.9-1-TR leaves fewer triangles than
+ *       0.2-1-TR).
  *   R2  p in edge sampling is the probability that an edge is deleted
  *       (Table `tab:theory-table`: (1-p)m edges remain; Table `tab:tcv`:
  *       the uniform columns scale as (1-p)^3).
