@@ -6,7 +6,7 @@ Calls only oracle/ (and the seeded input generator).  Usage:
     python tests/golden/make_oracle_digests.py [case ...]
 Cases: rmat20_tr_p0.2 rmat20_tr_p0.5 rmat20_tr_p0.8 rmat20_es_p0.5
        rmat20_tr2_p0.5 rmat20_mctr_p0.5 rmat20_eotr_p0.5 rmat24_tr_p0.5 rmat24_es_p0.5
-       rmat24_tr2_p0.5 rmat24_spectral_p0.5
+       rmat24_tr2_p0.5 rmat24_spectral_p0.5 rmat24_mctr_p0.5
 (tr: Triangle p-1-Reduction, es: uniform edge sampling, tr2: Triangle
 p-2-Reduction, mctr: Min-Count Triangle p-1-Reduction, eotr: Edge-Once
 Triangle p-1-Reduction, spectral: spectral sparsification with upsilon =
@@ -36,6 +36,7 @@ CASES = {
     "rmat24_es_p0.5": (24, "es", 0.5),
     "rmat24_tr2_p0.5": (24, "tr2", 0.5),
     "rmat24_spectral_p0.5": (24, "spectral", 0.5),
+    "rmat24_mctr_p0.5": (24, "mctr", 0.5),
 }
 GEN_SEED, OP_SEED, EDGE_FACTOR = 1, 1, 16
 

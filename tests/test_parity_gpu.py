@@ -325,6 +325,12 @@ def test_rmat24_tr2_full(slim, rmat24):
     _check_digest(slim, rmat24, "rmat24_tr2_p0.5")
 
 
+def test_rmat24_mctr_full(slim, rmat24):
+    """R-MAT scale 24: Min-Count p-1-Reduction (counting pass + selection)
+    against the oracle's stored digest."""
+    _check_digest(slim, rmat24, "rmat24_mctr_p0.5")
+
+
 
 # ------------------------------- Triangle p-2 and Min-Count p-1 variants
 
