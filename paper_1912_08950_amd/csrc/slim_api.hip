@@ -144,6 +144,7 @@ SetLayout set_layout(const SetShape& S) {
   const uint64_t nt = std::max(S.n_c, S.n_u);
   L.tile_cnt = c.take<uint32_t>(nt + 1);
   L.tile_base = c.take<uint64_t>(nt + 1);
+  L.masks = c.take<uint64_t>(nt * (uint64_t)kChunks);
   uint64_t st = scan_tmp_elems(nt);
   if (S.has_tr) {
     const uint64_t n = S.N, m = S.NNZ / 2;
@@ -332,7 +333,8 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
     uint32_t* dag_col = at<uint32_t>(ws, L.dag_col);
     uint2* dag_rng = at<uint2>(ws, L.dag_rng);
     uint32_t* rcol = at<uint32_t>(ws, L.rcol);
-    orient(row_off, col, rank, rcol, gu, t0u, recs_u, S.n_u, tile_cnt, tile_base, scan_tmp, s);
+    orient(row_off, col, rank, rcol, gu, t0u, recs_u, S.n_u, tile_cnt, at<uint64_t>(ws, L.masks),
+           tile_base, scan_tmp, s);
     dag_ranges(order, fstart, S.N, dag_rng, s);
     sort_rows(dag_rng, S.N, dag_col, at<uint32_t>(ws, L.sort_lists),
               at<uint32_t>(ws, L.sort_counts), num_cu, s);
@@ -388,7 +390,8 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
     }
     prof_begin(profile, "compact", s);
   }
-  compact_out(row_off, col, eid, del, S.NNZ / 2, gd, t0c, recs_c, S.n_c, tile_cnt, tile_base,
+  compact_out(row_off, col, eid, del, S.NNZ / 2, gd, t0c, recs_c, S.n_c, tile_cnt,
+              at<uint64_t>(ws, L.masks), tile_base,
               scan_tmp, s);
   write_stats(gd, S.count, t0c, counters, tile_base, s);
   prof_end(profile, s);
@@ -425,7 +428,8 @@ int eo_finish(const SetShape& S, const SetLayout& L, const Tuning& knobs, int nu
     const uint64_t* t0c = at<uint64_t>(ws, L.t0c);
     uint64_t* tile_base = at<uint64_t>(ws, L.tile_base);
     compact_out(row_off, col, at<uint32_t>(ws, L.eid), at<uint32_t>(ws, L.del), S.NNZ / 2, gd,
-                t0c, at<TileRec>(ws, L.recs_c), S.n_c, at<uint32_t>(ws, L.tile_cnt), tile_base,
+                t0c, at<TileRec>(ws, L.recs_c), S.n_c, at<uint32_t>(ws, L.tile_cnt),
+                at<uint64_t>(ws, L.masks), tile_base,
                 at<uint64_t>(ws, L.scan_tmp), s);
     write_stats(gd, S.count, t0c, at<uint64_t>(ws, L.counters), tile_base, s);
   }

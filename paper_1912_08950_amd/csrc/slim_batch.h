@@ -42,7 +42,7 @@ struct SetLayout {
   uint64_t gd, t0c, t0t, t0u, vt0, et0, hdr_bytes;
   uint64_t urow, ucol;
   uint64_t recs_c, recs_u, recs_t;
-  uint64_t tile_cnt, tile_base, scan_tmp;
+  uint64_t tile_cnt, tile_base, scan_tmp, masks;
   uint64_t ka, va, kb, vb, rank, rcol, hist, hist_scan;
   uint64_t fstart, dag_rng, dag_col, eid, del, counters;
   uint64_t sort_lists, sort_counts, tri_ctr, tcount;

@@ -77,16 +77,18 @@ void gather(const GDesc* gd, uint32_t count, const uint64_t* vtile0, const uint6
 // rcol[j] = rank of col[j] for every entry.
 void orient(const int64_t* row_off, const uint32_t* col, const uint32_t* rank, uint32_t* rcol,
             const GDesc* gd_union, const uint64_t* tile0, const TileRec* recs, uint64_t ntiles,
-            uint32_t* tile_cnt, uint64_t* tile_base, uint64_t* scan_tmp, hipStream_t s);
+            uint32_t* tile_cnt, uint64_t* masks, uint64_t* tile_base, uint64_t* scan_tmp,
+            hipStream_t s);
 void dag_ranges(const uint32_t* order, const uint32_t* fstart, uint64_t n, uint2* dag_rng,
                 hipStream_t s);
 // Output CSRs of every graph of the set: TR graphs keep the entries whose
 // edge is unmarked, ES graphs the entries whose edge is not sampled out.
-// eid/del may be NULL when the set has no TR graph.
+// eid/del may be NULL when the set has no TR graph.  masks: kChunks words per
+// tile (the count pass's ballots, read back by the scatter pass).
 void compact_out(const int64_t* row_off, const uint32_t* col, const uint32_t* eid,
                  const uint32_t* del, uint64_t m, const GDesc* gd, const uint64_t* tile0,
-                 const TileRec* recs, uint64_t ntiles, uint32_t* tile_cnt, uint64_t* tile_base,
-                 uint64_t* scan_tmp, hipStream_t s);
+                 const TileRec* recs, uint64_t ntiles, uint32_t* tile_cnt, uint64_t* masks,
+                 uint64_t* tile_base, uint64_t* scan_tmp, hipStream_t s);
 // Per-graph stats from the triangle counters (2 per graph, may be NULL) and
 // the compaction's tile scan.
 void write_stats(const GDesc* gd, uint32_t count, const uint64_t* tile0,

@@ -535,10 +535,13 @@ struct OutPolicy {
   }
 };
 
+// The count pass keeps the ballot of every 64-entry chunk (masks, 512 B per
+// tile), so the scatter pass neither recomputes the flags (Philox draws,
+// bitmap gathers) nor needs the rows of its entries.
 template <class P>
 __global__ __launch_bounds__(kBlock) void k_compact_count(P p, const int64_t* row_off,
                                                           const GDesc* gd, const TileRec* recs,
-                                                          uint32_t* tile_cnt) {
+                                                          uint32_t* tile_cnt, uint64_t* masks) {
   __shared__ TileRows L;
   __shared__ uint32_t wsum[kWavesPerBlock];
   const TileRec R = recs[blockIdx.x];
@@ -552,7 +555,9 @@ __global__ __launch_bounds__(kBlock) void k_compact_count(P p, const int64_t* ro
     const int i = c * kWave + lane;
     bool f = false;
     if ((uint32_t)i < R.span) f = p.flag(x, (uint64_t)R.j0 + i, rows ? tile_row_of(L, i) : 0u);
-    cnt += __popcll(__ballot(f));
+    const uint64_t m = __ballot(f);
+    if (lane == 0) masks[(uint64_t)blockIdx.x * kChunks + c] = m;
+    cnt += __popcll(m);
   }
   if (lane == 0) wsum[w] = cnt;
   __syncthreads();
@@ -571,26 +576,25 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(P p, const int64_t* 
                                                             const GDesc* gd,
                                                             const uint64_t* tile0,
                                                             const TileRec* recs,
-                                                            const uint64_t* tile_base) {
+                                                            const uint64_t* tile_base,
+                                                            const uint64_t* masks) {
   __shared__ TileRows L;
   __shared__ uint64_t cmask[kChunks];
   __shared__ uint32_t cbase[kChunks + 1];
   const TileRec R = recs[blockIdx.x];
   const GDesc& G = gd[R.g];
   const typename P::Ctx x = p.ctx(G);
-  const bool rows = p.needs_rows(G);
+  // rows only for the weights of spectral sparsification
+  const bool rows = P::kWeights && G.out_w && G.op == SLIM_OP_SPECTRAL;
   const int w = threadIdx.x / kWave, lane = lane_id();
   if (rows) tile_rows(row_off, R.j0, R.lo, R.hi, L);
   uint32_t fbits = 0;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     const int c = w + k * kWavesPerBlock;
-    const int i = c * kWave + lane;
-    bool f = false;
-    if ((uint32_t)i < R.span) f = p.flag(x, (uint64_t)R.j0 + i, rows ? tile_row_of(L, i) : 0u);
-    const uint64_t m = __ballot(f);
+    const uint64_t m = masks[(uint64_t)blockIdx.x * kChunks + c];  // the count pass's ballot
     if (lane == 0) cmask[c] = m;
-    if (f) fbits |= 1u << k;
+    if ((m >> lane) & 1u) fbits |= 1u << k;
   }
   __syncthreads();
   if (w == 0) {
@@ -614,8 +618,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(P p, const int64_t* 
       if (pos < cap) {  // always true for inputs that meet the contract
         out[pos] = p.value(x, j);
         if constexpr (P::kWeights)
-          if (G.out_w && G.op == SLIM_OP_SPECTRAL)
-            G.out_w[pos] = p.weight(x, j, tile_row_of(L, c * kWave + lane));
+          if (rows) G.out_w[pos] = p.weight(x, j, tile_row_of(L, c * kWave + lane));
       }
     }
   }
@@ -640,22 +643,24 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(P p, const int64_t* 
 template <class Pc, class Ps, typename OffT>
 void compact(const Pc& pc, const Ps& ps, const int64_t* row_off, const GDesc* gd,
              const uint64_t* tile0, const TileRec* recs, uint64_t ntiles, uint32_t* tile_cnt,
-             uint64_t* tile_base, uint64_t* scan_tmp, hipStream_t s) {
+             uint64_t* masks, uint64_t* tile_base, uint64_t* scan_tmp, hipStream_t s) {
   hipLaunchKernelGGL(k_compact_count<Pc>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, pc,
-                     row_off, gd, recs, tile_cnt);
+                     row_off, gd, recs, tile_cnt, masks);
   scan_excl<uint32_t>(tile_cnt, ntiles, tile_base, scan_tmp, s);
   hipLaunchKernelGGL((k_compact_scatter<Ps, OffT>), dim3((unsigned)ntiles), dim3(kBlock), 0, s,
-                     ps, row_off, gd, tile0, recs, (const uint64_t*)tile_base);
+                     ps, row_off, gd, tile0, recs, (const uint64_t*)tile_base,
+                     (const uint64_t*)masks);
 }
 
 void orient(const int64_t* row_off, const uint32_t* col, const uint32_t* rank, uint32_t* rcol,
             const GDesc* gd_union, const uint64_t* tile0, const TileRec* recs, uint64_t ntiles,
-            uint32_t* tile_cnt, uint64_t* tile_base, uint64_t* scan_tmp, hipStream_t s) {
+            uint32_t* tile_cnt, uint64_t* masks, uint64_t* tile_base, uint64_t* scan_tmp,
+            hipStream_t s) {
   OrientCountPolicy pc{col, rank, rcol};
   OrientScatterPolicy ps{rcol, rank};
   compact<OrientCountPolicy, OrientScatterPolicy, uint32_t>(pc, ps, row_off, gd_union, tile0, recs,
-                                                            ntiles, tile_cnt, tile_base, scan_tmp,
-                                                            s);
+                                                            ntiles, tile_cnt, masks, tile_base,
+                                                            scan_tmp, s);
 }
 
 __global__ void k_dag_rng(const uint32_t* order, const uint32_t* fstart, uint64_t n,
@@ -675,10 +680,10 @@ void dag_ranges(const uint32_t* order, const uint32_t* fstart, uint64_t n, uint2
 
 void compact_out(const int64_t* row_off, const uint32_t* col, const uint32_t* eid,
                  const uint32_t* del, uint64_t m, const GDesc* gd, const uint64_t* tile0,
-                 const TileRec* recs, uint64_t ntiles, uint32_t* tile_cnt, uint64_t* tile_base,
-                 uint64_t* scan_tmp, hipStream_t s) {
+                 const TileRec* recs, uint64_t ntiles, uint32_t* tile_cnt, uint64_t* masks,
+                 uint64_t* tile_base, uint64_t* scan_tmp, hipStream_t s) {
   OutPolicy p{col, eid, del, row_off, m};
-  compact<OutPolicy, OutPolicy, int64_t>(p, p, row_off, gd, tile0, recs, ntiles, tile_cnt,
+  compact<OutPolicy, OutPolicy, int64_t>(p, p, row_off, gd, tile0, recs, ntiles, tile_cnt, masks,
                                          tile_base, scan_tmp, s);
 }
 
