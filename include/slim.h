@@ -243,7 +243,9 @@ SLIM_API int slim_batch_workspace_size(const slim_batch_t* b, uint64_t* bytes);
  * Run every job of the batch on `stream`.  outs[g] receives graph g's
  * result (out arrays as in slim_triangle_reduce).  d_ws: at least
  * slim_batch_workspace_size bytes, 256-byte aligned.  Runs that share a
- * batch or a workspace must not overlap.  Errors: SLIM_EINVAL, SLIM_ENOMEM
+ * batch or a workspace must not overlap.  A batch with a SLIM_OP_EOTR job
+ * waits for `stream` before it returns (its rounds past the captured ones,
+ * if any, then run as direct launches).  Errors: SLIM_EINVAL, SLIM_ENOMEM
  * (workspace too small), SLIM_EDEVICE.
  */
 SLIM_API int slim_batch_run(slim_batch_t* b, void* d_ws, uint64_t ws_bytes, const slim_out_t* outs,

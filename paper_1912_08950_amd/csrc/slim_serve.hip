@@ -456,12 +456,22 @@ int slim_serve_create(const slim_serve_cfg_t* cfg, slim_server_t** out) {
   }
   S->arena.set_cap(S->cfg.hbm_budget_bytes + S->cfg.hbm_budget_bytes / 8);
   S->workers.resize(S->cfg.n_streams);
+  // pinned staging sized for the largest batch up front: growing it later
+  // would free pinned memory, which waits for the device
+  SetShape big;
+  big.count = std::min<uint32_t>(S->cfg.max_batch, 65536);
+  const uint64_t hdr_max = set_layout(big).hdr_bytes;
   for (auto& W : S->workers) {
-    if (hipStreamCreateWithFlags(&W.stream, hipStreamNonBlocking) != hipSuccess) {
-      for (auto& V : S->workers)
+    if (hipStreamCreateWithFlags(&W.stream, hipStreamNonBlocking) != hipSuccess ||
+        !grow_pinned(&W.pin_hdr, &W.pin_hdr_bytes, hdr_max) ||
+        !grow_pinned(&W.pin_stats, &W.pin_stats_bytes, sizeof(slim_stats_t) * big.count)) {
+      for (auto& V : S->workers) {
         if (V.stream) (void)hipStreamDestroy(V.stream);
+        if (V.pin_hdr) (void)hipHostFree(V.pin_hdr);
+        if (V.pin_stats) (void)hipHostFree(V.pin_stats);
+      }
       delete S;
-      return fail(SLIM_EDEVICE, "serve: stream creation failed");
+      return fail(SLIM_EDEVICE, "serve: stream or pinned buffer creation failed");
     }
   }
   for (int i = 0; i < (int)S->workers.size(); ++i)
