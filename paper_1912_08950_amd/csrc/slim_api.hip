@@ -175,8 +175,8 @@ SetLayout set_layout(const SetShape& S) {
       L.closed = c.take<uint32_t>(ceil_div(m, 32) + 1);
       L.eo_und = c.take<uint64_t>(kEoMaxRounds + 1);
       L.eo_live = c.take<uint32_t>(S.n_tri[0]);
-      L.eo_list = c.take<uint4>(2 * m);  // one triangle per edge
-      L.eo_misc = c.take<uint64_t>(2);
+      L.eo_list = c.take<uint4>(2 * 2 * kEoListPerEdge * m);  // two lists
+      L.eo_misc = c.take<uint64_t>(3);
     }
   }
   L.scan_tmp = c.take<uint64_t>(st + 1);
@@ -257,8 +257,8 @@ void eo_rounds(const SetShape& S, const SetLayout& L, const Tuning& knobs, int n
   a.eo_live = at<uint32_t>(ws, L.eo_live);
   a.eo_list = at<uint4>(ws, L.eo_list);
   a.eo_list_cnt = at<uint64_t>(ws, L.eo_misc);
-  a.eo_state = reinterpret_cast<uint32_t*>(at<uint64_t>(ws, L.eo_misc) + 1);
-  a.eo_cap = S.NNZ / 2;
+  a.eo_state = reinterpret_cast<uint32_t*>(at<uint64_t>(ws, L.eo_misc) + 2);
+  a.eo_cap = kEoListPerEdge * (S.NNZ / 2);
   a.gcount = S.count;
   for (uint32_t r = r0; r <= r1; ++r) {
     eo_clear_bids(a.minkey, a.closed, S.NNZ / 2, a.eo_und, r, s);
@@ -384,7 +384,7 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
       fill_u32(reinterpret_cast<uint32_t*>(at<uint64_t>(ws, L.eo_und)), 2 * (kEoMaxRounds + 1),
                0, s);
       fill_u32(at<uint32_t>(ws, L.eo_live), S.n_t(knobs.tri_tile), 0, s);
-      fill_u32(reinterpret_cast<uint32_t*>(at<uint64_t>(ws, L.eo_misc)), 4, 0, s);
+      fill_u32(reinterpret_cast<uint32_t*>(at<uint64_t>(ws, L.eo_misc)), 6, 0, s);
       eo_rounds(S, L, knobs, num_cu, ws, a, 1, (uint32_t)knobs.eo_rounds, s);
       prof_end(profile, s);
     }

@@ -125,10 +125,11 @@ struct TriArgs {
   uint32_t* closed;        // Edge-Once: bitmap of closed DAG edges
   uint64_t* eo_und;        // Edge-Once: undecided selected triangles of round r at [r]
   uint32_t* eo_live;       // Edge-Once: last round in which each tile bid
-  uint4* eo_list;          // Edge-Once: undecided triangles, two records each
-  uint64_t* eo_list_cnt;   // Edge-Once: records appended to eo_list
+  uint4* eo_list;          // Edge-Once: two lists of undecided triangles (two
+                           //   uint4 each), eo_cap triangles apart
+  uint64_t* eo_list_cnt;   // Edge-Once: triangles written to list 0 and list 1
   uint32_t* eo_state;      // Edge-Once: [0] = round that listed the triangles (0: none)
-  uint64_t eo_cap;         // Edge-Once: capacity of eo_list in triangles
+  uint64_t eo_cap;         // Edge-Once: capacity of each list in triangles
   uint32_t gcount;         // graphs of the set (gd[0 .. gcount))
   uint32_t pass;           // 0: Min-Count counting, 1: selection and marks,
                            // 2: Edge-Once bids
@@ -158,14 +159,24 @@ __host__ __device__ inline bool op_valid(int op) {
 // counter array (the rounds of greedy parallel maximal independent set with
 // random priorities grow as log of the triangle count).
 constexpr uint32_t kEoMaxRounds = 1024;
+// Capacity of each Edge-Once list in triangles per DAG edge.  The bidding
+// pass starts the list once the undecided triangles fit (R-MAT graphs keep
+// about a third of them per round, so three per edge saves two listing
+// passes over one per edge); later rounds copy the survivors from one list
+// into the other, so their cost falls with the undecided count.  The two
+// lists take 2 * 32 * kEoListPerEdge bytes of workspace per edge.
+constexpr uint64_t kEoListPerEdge = 3;
 void eo_clear_bids(uint64_t* minkey, uint32_t* closed, uint64_t m, const uint64_t* eo_und,
                    uint32_t round, hipStream_t s);
 // Acceptance of round a.round by an edge-parallel kernel over the n union
 // vertices (returns at once once the triangles are listed).
 void eo_accept_edges(const TriArgs& a, uint64_t n, int num_cu, hipStream_t s);
-// Bids and acceptance of round a.round on the triangle list (both return at
-// once unless the list was started in an earlier round; acceptance also in
-// the listing round).
+// Bids and acceptance of round a.round on the triangle lists (both return
+// at once unless the list was started in an earlier round; acceptance also
+// in the listing round).  Round r after the listing round L bids from list
+// (r - L - 1) mod 2 and copies the triangles that bid into the other list,
+// which its acceptance then reads; the listing round's acceptance reads
+// list 0.
 void eo_list_round(const TriArgs& a, int num_cu, hipStream_t s);
 
 // Scheduling knobs; never change results.

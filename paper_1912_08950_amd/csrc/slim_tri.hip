@@ -40,9 +40,11 @@
 // as (word 2, a, b, c) does, and the rounds reach the set that the walk in
 // that priority order reaches.  Closed in-edges are not scanned and closed
 // out-list entries are not hashed, so later rounds list fewer triangles.
-// Once the undecided triangles fit a list of one record per edge, the
-// bidding pass that finds them appends them, and all later rounds run over
-// the list (two small kernels) instead of listing triangles again.
+// Once the undecided triangles fit a list (kEoListPerEdge records per
+// edge), the bidding pass that finds them appends them, and all later rounds
+// run over the list (two small kernels) instead of listing triangles again;
+// each of those rounds copies its bidders into a second list, which the
+// next round reads, so a round costs in proportion to the undecided count.
 #include <type_traits>
 
 #include "slim_internal.h"
@@ -873,9 +875,13 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
         reinterpret_cast<uint32_t*>(a.eo_list + 2 * (C.wcur + i))[0] = kDead;
 }
 
-// ---- Edge-Once rounds on the triangle list: records {e_yx, e_xw, e_yw,
-// e_del} {word 2, third vertex of each of the three edges}; a record whose
-// triangle is decided (or a reserved slot that stayed unused) gets e_yx = kDead.
+// ---- Edge-Once rounds on the triangle lists: records {e_yx, e_xw, e_yw,
+// e_del} {word 2, third vertex of each of the three edges}.  In list 0 a
+// reserved slot that stayed unused has e_yx = kDead.  Round r after the
+// listing round L bids from list (r - L - 1) mod 2 and copies each triangle
+// that bids (none of its edges closed) into the other list; a triangle whose
+// edge closed is decided and dropped, so each round reads only the last
+// round's bidders.
 constexpr int kListBlock = 256;
 
 // Bids on the list start the round after the listing round, acceptance on
@@ -885,29 +891,63 @@ __device__ __forceinline__ bool eo_listed_round(const TriArgs& a, bool accept) {
   return listed != 0 && (listed < a.round || (accept && listed == a.round));
 }
 
+// Records a wave takes at a time: it counts the ones that will bid, reserves
+// that many slots of the other list with one atomic, then bids and copies
+// them (one atomic per 64 records on the shared counter serialized the
+// kernel).
+constexpr uint32_t kListSpan = 16 * kWave;
+
+__device__ __forceinline__ bool eo_list_live(const TriArgs& a, const uint4& r0) {
+  return r0.x != kDead && !bit_get(a.closed, r0.x) && !bit_get(a.closed, r0.y) &&
+         !bit_get(a.closed, r0.z);
+}
+
 __global__ __launch_bounds__(kListBlock) void k_eo_list_bid(TriArgs a) {
   if (!eo_listed_round(a, false) || a.eo_und[a.round - 1] == 0) return;
   __shared__ uint64_t red[kListBlock / kWave];
-  uint64_t n = *a.eo_list_cnt;
+  const uint32_t src = (a.round - a.eo_state[0] - 1) & 1u, dst = src ^ 1u;
+  const uint4* from = a.eo_list + (uint64_t)src * 2 * a.eo_cap;
+  uint4* to = a.eo_list + (uint64_t)dst * 2 * a.eo_cap;
+  uint64_t n = a.eo_list_cnt[src];
   if (n > a.eo_cap) n = a.eo_cap;
+  const uint32_t lane = lane_id();
+  const uint64_t waves = (uint64_t)gridDim.x * (kListBlock / kWave);
   uint64_t und = 0;
-  for (uint64_t i = blockIdx.x * (uint64_t)kListBlock + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * kListBlock) {
-    const uint4 r0 = a.eo_list[2 * i];
-    if (r0.x == kDead) continue;
-    if (bit_get(a.closed, r0.x) || bit_get(a.closed, r0.y) || bit_get(a.closed, r0.z)) {
-      reinterpret_cast<uint32_t*>(a.eo_list + 2 * i)[0] = kDead;
-      continue;
+  for (uint64_t b = (blockIdx.x * (uint64_t)(kListBlock / kWave) + threadIdx.x / kWave) * kListSpan;
+       b < n; b += waves * kListSpan) {
+    const uint64_t e = b + kListSpan < n ? b + kListSpan : n;
+    uint64_t cnt = 0;
+    for (uint64_t i = b + lane; i < e; i += kWave) cnt += eo_list_live(a, from[2 * i]);
+    cnt = wave_sum64(cnt);
+    if (cnt == 0) continue;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd((unsigned long long*)&a.eo_list_cnt[dst], (unsigned long long)cnt);
+    base = __shfl(base, 0, kWave);
+    // the same records pass the same test again (this kernel changes no
+    // closed bit), so exactly cnt slots from base are written; the first
+    // lane has the lowest index, so it is in every iteration another lane is
+    for (uint64_t i = b + lane; i < e; i += kWave) {
+      const uint4 r0 = from[2 * i];
+      const bool live = eo_list_live(a, r0);
+      const uint64_t mask = __ballot(live);
+      if (live) {
+        const uint4 r1 = from[2 * i + 1];
+        const uint64_t hi = (uint64_t)r1.x << 32;
+        eo_bid(a.minkey + r0.x, hi | r1.y);
+        eo_bid(a.minkey + r0.y, hi | r1.z);
+        eo_bid(a.minkey + r0.z, hi | r1.w);
+        ++und;
+        const uint64_t j = base + __popcll(mask & lanemask_lt());
+        if (j < a.eo_cap) {  // j < n <= eo_cap: at most every source record bids
+          to[2 * j] = r0;
+          to[2 * j + 1] = r1;
+        }
+      }
+      base += __popcll(mask);
     }
-    const uint4 r1 = a.eo_list[2 * i + 1];
-    const uint64_t hi = (uint64_t)r1.x << 32;
-    eo_bid(a.minkey + r0.x, hi | r1.y);
-    eo_bid(a.minkey + r0.y, hi | r1.z);
-    eo_bid(a.minkey + r0.z, hi | r1.w);
-    ++und;
   }
   const uint64_t t = wave_sum64(und);
-  if (lane_id() == 0) red[threadIdx.x / kWave] = t;
+  if (lane == 0) red[threadIdx.x / kWave] = t;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint64_t s = 0;
@@ -917,14 +957,22 @@ __global__ __launch_bounds__(kListBlock) void k_eo_list_bid(TriArgs a) {
 }
 
 __global__ __launch_bounds__(kListBlock) void k_eo_list_accept(TriArgs a) {
-  if (!eo_listed_round(a, true) || a.eo_und[a.round] == 0) return;
-  uint64_t n = *a.eo_list_cnt;
+  if (!eo_listed_round(a, true)) return;
+  const uint32_t listed = a.eo_state[0];
+  // the list this round's bids came from has been read in full: clear its
+  // count for the next round, which copies into it
+  const uint32_t src = (a.round - listed - 1) & 1u;
+  if (a.round > listed && blockIdx.x == 0 && threadIdx.x == 0) a.eo_list_cnt[src] = 0;
+  if (a.eo_und[a.round] == 0) return;
+  const uint32_t cur = a.round == listed ? 0u : src ^ 1u;
+  const uint4* list = a.eo_list + (uint64_t)cur * 2 * a.eo_cap;
+  uint64_t n = a.eo_list_cnt[cur];
   if (n > a.eo_cap) n = a.eo_cap;
   for (uint64_t i = blockIdx.x * (uint64_t)kListBlock + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * kListBlock) {
-    const uint4 r0 = a.eo_list[2 * i];
+    const uint4 r0 = list[2 * i];
     if (r0.x == kDead) continue;
-    const uint4 r1 = a.eo_list[2 * i + 1];
+    const uint4 r1 = list[2 * i + 1];
     const uint64_t hi = (uint64_t)r1.x << 32;
     if (a.minkey[r0.x] != (hi | r1.y) || a.minkey[r0.y] != (hi | r1.z) ||
         a.minkey[r0.z] != (hi | r1.w))
@@ -933,7 +981,6 @@ __global__ __launch_bounds__(kListBlock) void k_eo_list_accept(TriArgs a) {
     bit_set(a.closed, r0.y);
     bit_set(a.closed, r0.z);
     bit_set(a.del, r0.w);
-    reinterpret_cast<uint32_t*>(a.eo_list + 2 * i)[0] = kDead;
   }
 }
 
