@@ -168,10 +168,12 @@ SLIM_API int slim_edge_sample(const slim_graph_t* g, double p, uint64_t seed, vo
  *                 The number of rounds depends on the data: the call
  *                 synchronises `stream` (after each "eo_rounds" rounds, see
  *                 slim_tune_set) and returns when the output is complete;
- *                 so do batch runs and server batches holding such a job.  Every deleted edge
- *                 keeps a two-edge path (the output is a 2-spanner).
- *                 selected counts the Bernoulli selections, deleted the
- *                 considered triangles.
+ *                 so do batch runs and server batches holding such a job.
+ *                 Every deleted edge keeps a two-edge path (the output is a
+ *                 2-spanner).  selected counts the Bernoulli selections,
+ *                 deleted the considered triangles.  The workspace holds
+ *                 about 200 bytes per edge more than SLIM_OP_TR's, mostly
+ *                 two lists of the triangles still undecided in late rounds.
  */
 SLIM_API int slim_compress(const slim_graph_t* g, int op, double p, uint64_t seed, void* d_ws,
                            uint64_t ws_bytes, int64_t* d_out_row_off, uint32_t* d_out_col,
