@@ -58,6 +58,8 @@ def _load():
         fn.restype = ctypes.c_int
     lib.orc_triangle_reduce_x.argtypes = [u64, vp, vp, dbl, u64, ctypes.c_int, vp, vp, vp]
     lib.orc_triangle_reduce_x.restype = ctypes.c_int
+    lib.orc_triangle_reduce_eo.argtypes = [u64, vp, vp, dbl, u64, ctypes.c_uint32, vp, vp, vp]
+    lib.orc_triangle_reduce_eo.restype = ctypes.c_int
     lib.orc_spectral_sparsify.argtypes = [u64, vp, vp, dbl, u64, vp, vp, vp, vp]
     lib.orc_spectral_sparsify.restype = ctypes.c_int
     lib.orc_tr_rows.argtypes = [u64, vp, vp, dbl, u64, vp, u64, vp, vp]
@@ -139,6 +141,21 @@ def triangle_reduce_x(g, p: float, seed: int, variant: int):
 
     def fn(n, ro, col, p_, seed_, oro, ocol, st):
         return lib.orc_triangle_reduce_x(n, ro, col, p_, seed_, int(variant), oro, ocol, st)
+
+    return _run(fn, g, p, seed)
+
+
+def triangle_reduce_eo(g, p: float, seed: int, buckets: int = 1):
+    """Edge-Once Triangle p-1-Reduction (variant 4 of ``triangle_reduce_x``),
+    walking the selected triangles in ``buckets`` consecutive ranges of their
+    priority word so that only one range is held in memory at a time; the
+    result does not depend on ``buckets``.  Returns (row_off, col, stats)."""
+    lib = _load()
+    if int(buckets) < 1:
+        raise ValueError("buckets must be >= 1")
+
+    def fn(n, ro, col, p_, seed_, oro, ocol, st):
+        return lib.orc_triangle_reduce_eo(n, ro, col, p_, seed_, int(buckets), oro, ocol, st)
 
     return _run(fn, g, p, seed)
 
@@ -252,5 +269,7 @@ def edge_triangle_counts(g) -> np.ndarray:
     """t[j] = number of triangles containing the edge of CSR entry j."""
     ro, col = _arrays(g)
     t = np.zeros(max(g.nnz, 1), dtype=np.uint32)
-    _load().orc_edge_triangle_counts(g.n, ro.ctypes.data, col.ctypes.data, t.ctypes.data)
+    rc = _load().orc_edge_triangle_counts(g.n, ro.ctypes.data, col.ctypes.data, t.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"oracle edge_triangle_counts failed rc={rc}")
     return t[: g.nnz]

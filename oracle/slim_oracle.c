@@ -416,6 +416,14 @@ static void orc_trx_cb(void* vctx, uint32_t x, uint32_t y, uint32_t z) {
  * and edge choice k, sort them by (x2, a, b, c), then walk them in that
  * order; a triangle none of whose edges is considered yet deletes edge k
  * and marks its three edges considered, any other is skipped.
+ *
+ * With `buckets` > 1 the same walk is done in pieces, to bound the memory
+ * the selected triangles take: the x2 range [0, 2^32) is cut into `buckets`
+ * consecutive ranges, and for each range in increasing order the triangles
+ * are listed again, the selected ones whose x2 falls in it are collected,
+ * sorted and walked.  Every triangle of an earlier range precedes every
+ * triangle of a later one in the order (x2, a, b, c), so the walk visits the
+ * triangles in the same order as with one range.
  */
 typedef struct {
   uint32_t pri, a, b, c, k;
@@ -424,8 +432,9 @@ typedef struct {
 typedef struct {
   uint64_t thr;
   uint32_t key[2];
+  uint64_t pri_lo, pri_hi; /* collect selected triangles with x2 in [lo, hi) */
   orc_eo_tri* sel;
-  uint64_t T, selected, cap;
+  uint64_t T, selected, count, cap;
   int err;
 } orc_eo_ctx;
 
@@ -437,7 +446,9 @@ static void orc_eo_cb(void* vctx, uint32_t x, uint32_t y, uint32_t z) {
   orc_philox4x32_10(ctr, c->key, r);
   c->T++;
   if ((uint64_t)r[0] >= c->thr) return;
-  if (c->selected == c->cap) {
+  c->selected++;
+  if ((uint64_t)r[2] < c->pri_lo || (uint64_t)r[2] >= c->pri_hi) return;
+  if (c->count == c->cap) {
     uint64_t cap = c->cap ? 2 * c->cap : 1024;
     orc_eo_tri* s = (orc_eo_tri*)realloc(c->sel, cap * sizeof(orc_eo_tri));
     if (!s) {
@@ -448,7 +459,7 @@ static void orc_eo_cb(void* vctx, uint32_t x, uint32_t y, uint32_t z) {
     c->cap = cap;
   }
   orc_eo_tri t = {r[2], x, y, z, (uint32_t)(((uint64_t)r[1] * 3u) >> 32)};
-  c->sel[c->selected++] = t;
+  c->sel[c->count++] = t;
 }
 
 static int orc_eo_cmp(const void* pa, const void* pb) {
@@ -461,43 +472,58 @@ static int orc_eo_cmp(const void* pa, const void* pb) {
   return 0;
 }
 
-static int orc_triangle_reduce_eo(uint64_t n, const int64_t* row_off, const uint32_t* col,
-                                  double p, uint64_t seed, int64_t* out_row_off,
-                                  uint32_t* out_col, uint64_t* stats) {
+int orc_triangle_reduce_eo(uint64_t n, const int64_t* row_off, const uint32_t* col, double p,
+                           uint64_t seed, uint32_t buckets, int64_t* out_row_off,
+                           uint32_t* out_col, uint64_t* stats) {
   orc_graph g = {n, row_off, col};
   uint64_t nnz = (uint64_t)row_off[n];
-  orc_eo_ctx c;
-  memset(&c, 0, sizeof(c));
-  if (orc_threshold(p, &c.thr)) return -1;
-  c.key[0] = (uint32_t)seed;
-  c.key[1] = (uint32_t)(seed >> 32);
-  if (orc_for_each_triangle(&g, orc_eo_cb, &c) || c.err) {
-    free(c.sel);
-    return -3;
-  }
-  if (c.selected > 1) qsort(c.sel, c.selected, sizeof(orc_eo_tri), orc_eo_cmp);
+  uint64_t thr;
+  if (orc_threshold(p, &thr)) return -1;
+  if (buckets == 0) return -4;
   uint8_t* del = (uint8_t*)calloc(nnz > 0 ? nnz : 1, 1);
   uint8_t* considered = (uint8_t*)calloc(nnz > 0 ? nnz : 1, 1);
-  int err = !del || !considered;
-  for (uint64_t i = 0; i < c.selected && !err; ++i) {
-    const orc_eo_tri* t = &c.sel[i];
-    /* the edges in the order of R4: {a,b}, {a,c}, {b,c} */
-    int64_t slot[3] = {orc_edge_slot(&g, t->a, t->b), orc_edge_slot(&g, t->a, t->c),
-                       orc_edge_slot(&g, t->b, t->c)};
-    if (slot[0] < 0 || slot[1] < 0 || slot[2] < 0) {
+  if (!del || !considered) {
+    free(del);
+    free(considered);
+    return -2;
+  }
+  uint64_t T = 0, selected = 0;
+  int err = 0;
+  for (uint32_t bk = 0; bk < buckets && !err; ++bk) {
+    orc_eo_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.thr = thr;
+    c.key[0] = (uint32_t)seed;
+    c.key[1] = (uint32_t)(seed >> 32);
+    c.pri_lo = (uint64_t)bk * 4294967296ull / buckets;
+    c.pri_hi = (uint64_t)(bk + 1) * 4294967296ull / buckets;
+    if (orc_for_each_triangle(&g, orc_eo_cb, &c) || c.err) {
+      free(c.sel);
       err = 1;
       break;
     }
-    if (considered[slot[0]] || considered[slot[1]] || considered[slot[2]]) continue;
-    del[slot[t->k]] = 1;
-    considered[slot[0]] = considered[slot[1]] = considered[slot[2]] = 1;
+    T = c.T;
+    selected = c.selected;
+    if (c.count > 1) qsort(c.sel, c.count, sizeof(orc_eo_tri), orc_eo_cmp);
+    for (uint64_t i = 0; i < c.count; ++i) {
+      const orc_eo_tri* t = &c.sel[i];
+      /* the edges in the order of R4: {a,b}, {a,c}, {b,c} */
+      int64_t slot[3] = {orc_edge_slot(&g, t->a, t->b), orc_edge_slot(&g, t->a, t->c),
+                         orc_edge_slot(&g, t->b, t->c)};
+      if (slot[0] < 0 || slot[1] < 0 || slot[2] < 0) {
+        err = 1;
+        break;
+      }
+      if (considered[slot[0]] || considered[slot[1]] || considered[slot[2]]) continue;
+      del[slot[t->k]] = 1;
+      considered[slot[0]] = considered[slot[1]] = considered[slot[2]] = 1;
+    }
+    free(c.sel);
   }
-  free(c.sel);
   free(considered);
   if (err) {
-    const int rc = del ? -3 : -2;
     free(del);
-    return rc;
+    return -3;
   }
   uint64_t deleted = 0;
   for (uint64_t j = 0; j < nnz; ++j) deleted += del[j];
@@ -505,8 +531,8 @@ static int orc_triangle_reduce_eo(uint64_t n, const int64_t* row_off, const uint
   free(del);
   stats[0] = n;
   stats[1] = nnz / 2;
-  stats[2] = c.T;
-  stats[3] = c.selected;
+  stats[2] = T;
+  stats[3] = selected;
   stats[4] = deleted;
   stats[5] = nnz / 2 - deleted;
   return 0;
@@ -516,7 +542,7 @@ int orc_triangle_reduce_x(uint64_t n, const int64_t* row_off, const uint32_t* co
                           uint64_t seed, int variant, int64_t* out_row_off, uint32_t* out_col,
                           uint64_t* stats) {
   if (variant == 4)
-    return orc_triangle_reduce_eo(n, row_off, col, p, seed, out_row_off, out_col, stats);
+    return orc_triangle_reduce_eo(n, row_off, col, p, seed, 1, out_row_off, out_col, stats);
   if (variant < 1 || variant > 3) return -4;
   orc_graph g = {n, row_off, col};
   uint64_t nnz = (uint64_t)row_off[n];
@@ -536,7 +562,11 @@ int orc_triangle_reduce_x(uint64_t n, const int64_t* row_off, const uint32_t* co
       free(c.del);
       return -2;
     }
-    orc_edge_triangle_counts(n, row_off, col, tc);
+    if (orc_edge_triangle_counts(n, row_off, col, tc)) {
+      free(c.del);
+      free(tc);
+      return -3;
+    }
     c.tcount = tc;
   }
   if (orc_for_each_triangle(&g, orc_trx_cb, &c) || c.err) {
@@ -701,30 +731,41 @@ int orc_tr_rows(uint64_t n, const int64_t* row_off, const uint32_t* col, double 
 }
 
 /* ------------------------------------------ per-edge triangle counts
- * t[j] = |N(r) ∩ N(c)| for every CSR entry j = (r,c): the number of
- * triangles the undirected edge {r,c} lies in, by merging the two rows.
+ * t[j] = number of triangles of the input graph that contain the undirected
+ * edge of CSR entry j = (r,c) (the t_e of R9).  Every triangle is listed
+ * once (the forward listing above) and adds one to each of its three edges,
+ * counted at the copy in the row of the smaller id; the copy in the other
+ * row then takes the same count.  (Merging the two full rows of every entry
+ * gives the same numbers but costs the sum of squared degrees.)
  */
+typedef struct {
+  const orc_graph* g;
+  uint32_t* t;
+  int err;
+} orc_count_ctx;
+
+static void orc_count_cb(void* vctx, uint32_t x, uint32_t y, uint32_t z) {
+  orc_count_ctx* c = (orc_count_ctx*)vctx;
+  orc_sort3(&x, &y, &z);
+  int64_t slot[3] = {orc_edge_slot(c->g, x, y), orc_edge_slot(c->g, x, z),
+                     orc_edge_slot(c->g, y, z)};
+  for (int e = 0; e < 3; ++e) {
+    if (slot[e] < 0)
+      c->err = 1;
+    else
+      c->t[slot[e]]++;
+  }
+}
+
 int orc_edge_triangle_counts(uint64_t n, const int64_t* row_off, const uint32_t* col,
                              uint32_t* t) {
-  for (uint64_t r = 0; r < n; ++r) {
-    for (int64_t j = row_off[r]; j < row_off[r + 1]; ++j) {
-      uint32_t c = col[j];
-      uint32_t cnt = 0;
-      int64_t a = row_off[r], ae = row_off[r + 1];
-      int64_t b = row_off[c], be = row_off[c + 1];
-      while (a < ae && b < be) {
-        if (col[a] < col[b])
-          ++a;
-        else if (col[a] > col[b])
-          ++b;
-        else {
-          ++cnt;
-          ++a;
-          ++b;
-        }
-      }
-      t[j] = cnt;
-    }
-  }
+  orc_graph g = {n, row_off, col};
+  uint64_t nnz = (uint64_t)row_off[n];
+  memset(t, 0, (size_t)nnz * sizeof(uint32_t));
+  orc_count_ctx c = {&g, t, 0};
+  if (orc_for_each_triangle(&g, orc_count_cb, &c) || c.err) return -3;
+  for (uint64_t r = 0; r < n; ++r)
+    for (int64_t j = row_off[r]; j < row_off[r + 1]; ++j)
+      if ((uint64_t)col[j] < r) t[j] = t[orc_find(&g, col[j], (uint32_t)r)];
   return 0;
 }

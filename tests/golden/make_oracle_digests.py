@@ -6,12 +6,17 @@ Calls only oracle/ (and the seeded input generator).  Usage:
     python tests/golden/make_oracle_digests.py [case ...]
 Cases: rmat20_tr_p0.2 rmat20_tr_p0.5 rmat20_tr_p0.8 rmat20_es_p0.5
        rmat20_tr2_p0.5 rmat20_mctr_p0.5 rmat20_eotr_p0.5 rmat24_tr_p0.5 rmat24_es_p0.5
-       rmat24_tr2_p0.5 rmat24_spectral_p0.5 rmat24_mctr_p0.5
+       rmat24_tr2_p0.5 rmat24_spectral_p0.5 rmat24_mctr_p0.5 rmat24_eotr_p0.5
 (tr: Triangle p-1-Reduction, es: uniform edge sampling, tr2: Triangle
 p-2-Reduction, mctr: Min-Count Triangle p-1-Reduction, eotr: Edge-Once
 Triangle p-1-Reduction, spectral: spectral sparsification with upsilon =
 p m / n, the weights digested too)
+
+Edge-Once at scale 24 walks its 5.1e9 selected triangles in five ranges of
+the priority word (about 21 GB of host memory per range instead of 100 GB);
+the walk's order and result do not depend on the number of ranges.
 """
+import fcntl
 import hashlib
 import json
 import os
@@ -37,7 +42,9 @@ CASES = {
     "rmat24_tr2_p0.5": (24, "tr2", 0.5),
     "rmat24_spectral_p0.5": (24, "spectral", 0.5),
     "rmat24_mctr_p0.5": (24, "mctr", 0.5),
+    "rmat24_eotr_p0.5": (24, "eotr", 0.5),
 }
+EO_BUCKETS = {24: 5}
 GEN_SEED, OP_SEED, EDGE_FACTOR = 1, 1, 16
 
 
@@ -64,12 +71,17 @@ def main(names):
             ups = p * g.m / g.n
             ro, col, w, st = oracle.spectral_sparsify(g, ups, OP_SEED)
             w_sha = hashlib.sha256(np.ascontiguousarray(w, dtype="<f4").tobytes()).hexdigest()
-        elif op in ("tr2", "mctr", "eotr"):
+        elif op == "eotr":
+            ro, col, st = oracle.triangle_reduce_eo(g, p, OP_SEED, EO_BUCKETS.get(scale, 1))
+        elif op in ("tr2", "mctr"):
             ro, col, st = oracle.triangle_reduce_x(g, p, OP_SEED, {"tr2": 2, "mctr": 3, "eotr": 4}[op])
         else:
             fn = oracle.triangle_reduce if op == "tr" else oracle.edge_sample
             ro, col, st = fn(g, p, OP_SEED)
-        # read just before writing: other cases may have been written meanwhile
+        # read just before writing, under a lock: another run of this script
+        # may have written other cases meanwhile
+        lock = open(OUT + ".lock", "w")
+        fcntl.flock(lock, fcntl.LOCK_EX)
         data = json.load(open(OUT)) if os.path.exists(OUT) else {}
         data[name] = {
             "graph": f"rmat scale={scale} edge_factor={EDGE_FACTOR} seed={GEN_SEED}",
@@ -82,8 +94,12 @@ def main(names):
         if w_sha is not None:
             data[name]["weights_sha256"] = w_sha
             data[name]["upsilon"] = ups
+        if op == "eotr" and EO_BUCKETS.get(scale, 1) > 1:
+            data[name]["oracle_priority_ranges"] = EO_BUCKETS[scale]
         json.dump(data, open(OUT + ".tmp", "w"), indent=1, sort_keys=True)
         os.replace(OUT + ".tmp", OUT)
+        fcntl.flock(lock, fcntl.LOCK_UN)
+        lock.close()
         print(name, data[name], flush=True)
 
 

@@ -295,6 +295,58 @@ def test_es_symmetric_and_endpoints(cfg1):
     assert len(col1) == 0 and st1["deleted"] == cfg1.m and np.all(ro1 == 0)
 
 
+def test_es_decisions_match_definition():
+    """Edge by edge on a small graph: {a<b} is deleted iff Philox(a,b,0,1)
+    word 0 < floor(p 2^32), and both CSR copies follow that one decision
+    (section 4.2.2 kernel random_uniform with p the deletion probability)."""
+    g = gg.er(300, 12.0, 5)
+    for p, seed in ((0.5, 91), (0.2, 2**33 + 5), (0.9, 4)):
+        ro, col, st = O.edge_sample(g, p, seed)
+        kept = edge_set(ro, col)
+        key = (seed & 0xFFFFFFFF, seed >> 32)
+        thr = O.threshold(p)
+        gone = 0
+        for a, b in undirected(g.row_off, g.col):
+            deleted = O.philox4x32_10((a, b, 0, 1), key)[0] < thr
+            gone += deleted
+            assert ((a, b) in kept) == (not deleted) and ((b, a) in kept) == (not deleted)
+        assert st["deleted"] == gone and st["m_out"] == g.m - gone
+
+
+# ------------------------------------------------- input-contract checker
+
+def _csr(ro, col):
+    return gg.CSR(np.asarray(ro, dtype=np.int64), np.asarray(col, dtype=np.uint32))
+
+
+# a triangle 0-1-2 plus the edge 2-3, in a valid symmetric sorted CSR
+_VALID_RO = [0, 2, 4, 7, 8]
+_VALID_COL = [1, 2, 0, 2, 0, 1, 3, 2]
+
+
+@pytest.mark.parametrize("name,ro,col,code", [
+    ("offsets not starting at 0", [1, 2, 4, 7, 8], _VALID_COL, -2),
+    ("non-monotone offsets", [0, 2, 1, 7, 8], _VALID_COL, -3),
+    ("id >= n", [0, 2, 4, 7, 8], [1, 2, 0, 2, 0, 1, 4, 2], -4),
+    ("self-loop", [0, 2, 4, 7, 8], [0, 2, 0, 2, 0, 1, 3, 2], -5),
+    ("unsorted row", [0, 2, 4, 7, 8], [2, 1, 0, 2, 0, 1, 3, 2], -6),
+    ("duplicate in a row", [0, 2, 4, 7, 8], [1, 1, 0, 2, 0, 1, 3, 2], -6),
+    ("missing reverse copy", [0, 2, 4, 7, 7], [1, 2, 0, 2, 0, 1, 3], -7),
+    ("odd entry count", [0, 2, 4, 6, 7], [1, 2, 0, 2, 0, 1, 2], -7),
+])
+def test_validate_rejects_each_broken_contract(name, ro, col, code):
+    """The input contract (a simple undirected graph as a symmetric CSR with
+    strictly increasing rows): each broken clause gets its own nonzero code,
+    while the valid graph next to them passes."""
+    assert O.validate(_csr(_VALID_RO, _VALID_COL)) == 0
+    assert O.validate(_csr(ro, col)) == code, name
+
+
+def test_validate_accepts_valid_families(cfg1):
+    for g in (cfg1, gg.complete(7), gg.empty(5), gg.star(9), gg.rmat(10, 8, 3)):
+        assert O.validate(g) == 0
+
+
 # ------------------------------------------------- local per-row oracle
 
 @pytest.mark.parametrize("p,seed", [(0.5, 1), (0.2, 2), (1.0, 3)])
@@ -521,6 +573,20 @@ def test_eo_matches_rounds_of_local_minima(n, q, seed):
         keep, t, sel, nd, _ = brute_eo(g, p, s)
         assert undirected(ro, col) == keep and is_valid_csr(g.n, ro, col)
         assert (st["T"], st["selected"], st["deleted"]) == (t, sel, nd)
+
+
+@pytest.mark.parametrize("n,q,seed", [(12, 0.5, 2), (16, 0.7, 5), (20, 0.5, 9)])
+def test_eo_bucketed_walk_matches_rounds_of_local_minima(n, q, seed):
+    """The walk done in several consecutive ranges of the priority word
+    (what bounds its memory on large graphs) against the same independent
+    algorithm as above, for several range counts."""
+    g = gg.er(n, q * (n - 1), seed)
+    for p, s in ((1.0, 7), (0.6, 2**40 + 3)):
+        keep, t, sel, nd, _ = brute_eo(g, p, s)
+        for buckets in (1, 2, 3, 7, 64):
+            ro, col, st = O.triangle_reduce_eo(g, p, s, buckets)
+            assert undirected(ro, col) == keep and is_valid_csr(g.n, ro, col)
+            assert (st["T"], st["selected"], st["deleted"]) == (t, sel, nd)
 
 
 def test_eo_equals_p1_on_edge_disjoint_triangles():
