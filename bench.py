@@ -451,17 +451,6 @@ def main():
         v = float(slim.degree_kl(dg.row_off, bufs_out.out_row_off).cpu().item())
         return "inf" if math.isinf(v) else v
 
-    # Kullback-Leibler divergence of the output's PageRank distribution from
-    # the input's (Table `tab:pr-KL`'s metric; d = 0.85, 20 steps), on the device
-    pr_in = slim.pagerank(dg.row_off, dg.col)
-
-    def pagerank_kl_of(bufs_out):
-        k = int(bufs_out.out_row_off[-1].item())
-        pr_out = slim.pagerank(bufs_out.out_row_off, bufs_out.out_col[:k])
-        v = float(slim.kl_divergence(pr_in, pr_out).cpu().item())
-        del pr_out
-        return "inf" if math.isinf(v) else v
-
     t_in = stats["triangles"]
     ups = args.p * g.m / g.n  # upsilon = p m / n, the paper's average-degree choice
     variants = {"tr": {"ms": ms_per_step, "edges_per_s": g.m / (ms_per_step * 1e-3),
@@ -471,7 +460,6 @@ def main():
                                           ("spectral", slim.OP_SPECTRAL)]
     variants["tr"]["A_S_triangles"] = triangles_of(bufs) / t_in if t_in else None
     variants["tr"]["degree_kl_bits"] = degree_kl_of(bufs)
-    variants["tr"]["pagerank_kl_bits"] = pagerank_kl_of(bufs)
     for name, op in ops:
         vb = slim.Buffers(dg, op)
         param = ups if op == slim.OP_SPECTRAL else args.p
@@ -488,16 +476,15 @@ def main():
         vst = dict(zip(slim.STAT_KEYS, (int(x) for x in vb.stats.cpu().numpy())))
         variants[name] = {"ms": ms, "edges_per_s": g.m / (ms * 1e-3), "stats": vst,
                           "A_S_triangles": triangles_of(vb) / t_in if t_in else None,
-                          "degree_kl_bits": degree_kl_of(vb),
-                          "pagerank_kl_bits": pagerank_kl_of(vb)}
+                          "degree_kl_bits": degree_kl_of(vb)}
         if op == slim.OP_SPECTRAL:
             variants[name]["upsilon"] = ups
         log(f"{name}: {ms:.2f} ms {vst} A_S={variants[name]['A_S_triangles']} "
-            f"KL deg={variants[name]['degree_kl_bits']} pr={variants[name]['pagerank_kl_bits']}")
+            f"KL deg={variants[name]['degree_kl_bits']}")
         del vb
     variants["triangles_per_vertex_in"] = 3 * t_in / g.n
     result["variants"] = variants
-    del bufs, es_bufs, dg, pr_in
+    del bufs, es_bufs, dg
     torch.cuda.empty_cache()
     if args.batch_count > 0:
         result["batch"] = bench_batch(args, log)

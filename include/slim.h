@@ -211,8 +211,10 @@ SLIM_API int slim_spectral_sparsify(const slim_graph_t* g, double upsilon, uint6
  *
  * The first slim_batch_run captures the launch sequence into a HIP graph;
  * later runs with the same workspace and knobs replay it as one graph
- * launch (per-graph output pointers live in a device table that a run
- * refreshes with one host-to-device copy when they change).
+ * launch.  Per-graph descriptors (output pointers, tile prefixes) live in a
+ * table at the start of the workspace that every run refreshes with one
+ * host-to-device copy, so a workspace may serve other calls between two
+ * runs of a batch.
  */
 typedef struct slim_job_params {
   int32_t op;    /* any SLIM_OP_* code (SLIM_OP_SPECTRAL: p carries upsilon) */
@@ -271,6 +273,16 @@ SLIM_API int slim_batch_get(const slim_batch_t* b, const char* key, int64_t* val
  */
 SLIM_API int slim_batch_tune(slim_batch_t* b, void* d_ws, uint64_t ws_bytes, const slim_out_t* outs,
                              const char* cache_path, void* stream);
+/*
+ * Host copy of the per-graph counters of the batch's most recent run
+ * (per_graph: `count` records, in graph order; the same values the run wrote
+ * to outs[g].stats, kept in device memory that the batch owns, so it does
+ * not matter whether outs[g].stats was set).  Waits for that run to finish.
+ * The paper's per-graph quantities: n, m, T, the selected and deleted counts
+ * (section 4.3; A_S of section 5 uses T).  Errors: SLIM_EINVAL (NULL, no run
+ * yet), SLIM_EDEVICE.
+ */
+SLIM_API int slim_batch_stats(slim_batch_t* b, slim_stats_t* per_graph);
 /* Release a batch (NULL is ignored).  The caller synchronises the streams
  * of its runs first. */
 SLIM_API void slim_batch_free(slim_batch_t* b);
@@ -292,10 +304,13 @@ SLIM_API void slim_batch_free(slim_batch_t* b);
  * and (c) its share of its batch's workspace while the batch runs.  Jobs
  * are admitted while the sum of these reservations (each rounded up to an
  * allocation size class, the workspace share with 10% headroom) stays within
- * hbm_budget_bytes.  Device memory comes from a caching arena that the
- * server owns and frees at slim_serve_destroy; it reuses a cached block for
- * any request of at least half its size and trims its cache to keep the
- * memory it holds within 1.125 x the budget.
+ * hbm_budget_bytes.  Device memory comes from a sub-allocating arena that
+ * the server owns and frees at slim_serve_destroy: it takes chunks of 2 GiB
+ * (or one request's size, if larger) from the runtime, carves requests from
+ * them best-fit in 4 KiB units, and merges a freed range with free
+ * neighbours; a chunk goes back to the runtime only when it is entirely free
+ * and a new chunk would take the arena past 1.125 x the budget, so steady
+ * serving calls neither hipMalloc nor hipFree.
  */
 #define SLIM_HOST 0u   /* slim_job_t.where: CSR arrays in host memory */
 #define SLIM_DEVICE 1u /* slim_job_t.where: CSR arrays in device memory */
@@ -432,42 +447,6 @@ SLIM_API int slim_profile_read(slim_phase_t* out, int max, int* count);
 SLIM_API int slim_degree_kl_workspace(uint64_t n, uint64_t* bytes);
 SLIM_API int slim_degree_kl(const int64_t* d_row_off_p, const int64_t* d_row_off_q, uint64_t n,
                             void* d_ws, uint64_t ws_bytes, double* d_out, void* stream);
-
-/*
- * PageRank (Table `tab:problems`; Table `tab:pr-KL` compares the PageRank
- * distributions of original and compressed graphs): x = 1/n, then `iters`
- * Jacobi steps x'(v) = (1-d)/n + d * sum over neighbours u of x(u)/deg(u).
- * A vertex without edges passes nothing on (its share is not spread over
- * the graph), so the scores sum to at most 1.
- *   d_row_off, d_col  device CSR of the graph (n+1 offsets, columns).
- *   n         vertices, < 2^32 (n = 0: nothing to do).
- *   damping   d in [0, 1] (NaN or outside -> SLIM_EINVAL); 0.85 is usual.
- *   iters     number of steps (0 leaves x = 1/n).
- *   d_ws      device workspace of slim_pagerank_workspace(n) bytes,
- *             256-byte aligned (smaller -> SLIM_ENOMEM).
- *   d_pr      device double[n]: the scores.
- * Enqueued on `stream`; every sum runs in a fixed order, so the scores are
- * reproducible bit for bit.  Errors: SLIM_EINVAL, SLIM_ENOMEM, SLIM_EDEVICE.
- */
-SLIM_API int slim_pagerank_workspace(uint64_t n, uint64_t* bytes);
-SLIM_API int slim_pagerank(const int64_t* d_row_off, const uint32_t* d_col, uint64_t n,
-                           double damping, uint32_t iters, void* d_ws, uint64_t ws_bytes,
-                           double* d_pr, void* stream);
-
-/*
- * Kullback-Leibler divergence D_KL(P||Q) = sum_i P(i) log2(P(i)/Q(i)) in
- * bits (section 5) of two non-negative device vectors of n doubles, each
- * normalised to sum 1 (P = p / sum p, Q = q / sum q); +infinity when some
- * q_i = 0 < p_i.  Used on PageRank scores of a graph and its compression.
- *   d_ws   device workspace of slim_kl_divergence_workspace(n) bytes,
- *          256-byte aligned.
- *   d_out  device double[1].
- * Enqueued on `stream`, fixed summation order.  Errors: SLIM_EINVAL
- * (NULL pointers), SLIM_ENOMEM, SLIM_EDEVICE.
- */
-SLIM_API int slim_kl_divergence_workspace(uint64_t n, uint64_t* bytes);
-SLIM_API int slim_kl_divergence(const double* d_p, const double* d_q, uint64_t n, void* d_ws,
-                                uint64_t ws_bytes, double* d_out, void* stream);
 
 #ifdef __cplusplus
 }

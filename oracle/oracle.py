@@ -3,8 +3,7 @@
 Plain single-threaded reference for Triangle p-1-Reduction (Slim Graph,
 section 4.3), its p-2, Min-Count and Edge-Once variants, uniform edge
 sampling (section 4.2.2), spectral sparsification (section 4.2.1) and the
-accuracy metrics of section 5 (degree-distribution and PageRank KL
-divergence, in numpy).  Only tests/,
+degree-distribution Kullback-Leibler divergence of section 5 (in numpy).  Only tests/,
 ``__graft_entry__.smoke()`` and bench.py's ``cpu_baseline`` leg may import
 this module; the product path never does.  It shares no code with the GPU
 path.  The readings of the paper it implements are stated in the header of
@@ -228,41 +227,6 @@ def degree_kl(row_off_p, row_off_q) -> float:
             return float("inf")
         total += P[k] * math.log2(P[k] / Q[k])
     return total
-
-
-def pagerank(g, damping: float = 0.85, iters: int = 20) -> np.ndarray:
-    """PageRank scores in float64 (R12): x = 1/n, then `iters` Jacobi steps
-    x'(v) = (1-d)/n + d * sum over neighbours u of x(u)/deg(u); a vertex
-    without edges passes nothing on.  The neighbour sums are one sparse
-    matrix-vector product (scipy) per step."""
-    from scipy.sparse import csr_matrix
-    n = g.n
-    if n == 0:
-        return np.zeros(0)
-    ro = np.asarray(g.row_off, dtype=np.int64)
-    col = np.asarray(g.col, dtype=np.int64)
-    deg = np.diff(ro).astype(np.float64)
-    A = csr_matrix((np.ones(col.size), col, ro), shape=(n, n))
-    x = np.full(n, 1.0 / n)
-    for _ in range(iters):
-        contrib = np.divide(x, deg, out=np.zeros(n), where=deg > 0)
-        x = (1.0 - damping) / n + damping * (A @ contrib)
-    return x
-
-
-def kl_divergence(p, q) -> float:
-    """D_KL(P||Q) = sum_i P(i) log2(P(i)/Q(i)) (section 5, bits) of two
-    non-negative vectors, each normalised to sum 1; +inf if some
-    q_i = 0 < p_i."""
-    p = np.asarray(p, dtype=np.float64)
-    q = np.asarray(q, dtype=np.float64)
-    if p.size == 0:
-        return 0.0
-    P, Q = p / p.sum(), q / q.sum()
-    on = P > 0
-    if np.any(Q[on] == 0):
-        return float("inf")
-    return float(np.sum(P[on] * np.log2(P[on] / Q[on])))
 
 
 def edge_triangle_counts(g) -> np.ndarray:

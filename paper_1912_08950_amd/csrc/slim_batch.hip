@@ -105,11 +105,15 @@ struct slim_batch {
   bool use_graph = true;
   bool verbose = false;  // the tuner reports each candidate on stderr
   // header upload
-  std::vector<char> hdr, last_hdr;
+  std::vector<char> hdr;
   void* pinned = nullptr;
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
-  void* last_ws = nullptr;
+  // per-graph stats of the most recent run (device, one record per graph),
+  // and the event that marks the end of that run
+  slim_stats_t* dstats = nullptr;
+  hipEvent_t run_done = nullptr;
+  bool ran = false;
   // captured launch sequence
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -142,6 +146,8 @@ void build_header(slim_batch* b, void* ws, const slim_out_t* outs) {
     b->plan.gd[g].out_w = outs[g].weight;
   }
   fill_header(b->plan, b->layout, b->knobs, ws, b->hdr);
+  // the union descriptor carries the batch's own per-graph stats array
+  reinterpret_cast<GDesc*>(b->hdr.data() + b->layout.gd)[b->count].stats = b->dstats;
 }
 
 int check_run(const slim_batch* b, void* ws, uint64_t ws_bytes, const slim_out_t* outs) {
@@ -167,25 +173,30 @@ int run(slim_batch* b, void* ws, uint64_t ws_bytes, const slim_out_t* outs, hipS
   (void)hipGetLastError();
   build_header(b, ws, outs);
   const size_t hb = b->hdr.size();
-  if (ws != b->last_ws || b->hdr != b->last_hdr) {
-    // the pinned buffer may still feed the previous upload
-    if (b->upload_pending && hipEventSynchronize(b->upload_done) != hipSuccess)
-      return fail(SLIM_EDEVICE, "batch header: previous upload failed");
-    std::memcpy(b->pinned, b->hdr.data(), hb);
-    if (hipMemcpyAsync(ws, b->pinned, hb, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipEventRecord(b->upload_done, s) != hipSuccess)
-      return fail(SLIM_EDEVICE, "batch header upload failed");
-    b->upload_pending = true;
-    b->last_hdr = b->hdr;
-    b->last_ws = ws;
-  }
+  // The header is uploaded on every run: between two runs of this batch the
+  // workspace may have served another call, which writes its own header at
+  // the same place.
+  // The pinned buffer may still feed the previous upload.
+  if (b->upload_pending && hipEventSynchronize(b->upload_done) != hipSuccess)
+    return fail(SLIM_EDEVICE, "batch header: previous upload failed");
+  std::memcpy(b->pinned, b->hdr.data(), hb);
+  if (hipMemcpyAsync(ws, b->pinned, hb, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipEventRecord(b->upload_done, s) != hipSuccess)
+    return fail(SLIM_EDEVICE, "batch header upload failed");
+  b->upload_pending = true;
+  auto finish = [&]() -> int {
+    if (hipEventRecord(b->run_done, s) != hipSuccess)
+      return fail(SLIM_EDEVICE, "slim_batch_run: event record failed");
+    b->ran = true;
+    return hip_check("slim_batch_run");
+  };
   if (!b->use_graph) {  // direct launches: phases are timed when profiling is on
     prof_reset();
     run_set(b->plan.shape, b->layout, b->knobs, b->num_cu, ws, nullptr, nullptr, s, true);
     if (int rc = hip_check("slim_batch_run")) return rc;
     if (int rc = eo_finish(b->plan.shape, b->layout, b->knobs, b->num_cu, ws, nullptr, nullptr, s))
       return rc;
-    return hip_check("slim_batch_run");
+    return finish();
   }
   if (!b->exec || b->cap_ws != ws || !same_knobs(b->cap_knobs, b->knobs)) {
     drop_graph(b);
@@ -212,7 +223,7 @@ int run(slim_batch* b, void* ws, uint64_t ws_bytes, const slim_out_t* outs, hipS
   // Edge-Once rounds past the captured ones run as direct launches
   if (int rc = eo_finish(b->plan.shape, b->layout, b->knobs, b->num_cu, ws, nullptr, nullptr, s))
     return rc;
-  return hip_check("slim_batch_run");
+  return finish();
 }
 
 std::string tune_key(const slim_batch* b) {
@@ -307,7 +318,9 @@ int slim_batch_create(const slim_graph_t* const* graphs, const slim_job_params_t
     b->knobs = tuning();
   }
   if (hipHostMalloc(&b->pinned, b->layout.hdr_bytes, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&b->dstats, sizeof(slim_stats_t) * count) != hipSuccess ||
       hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->run_done, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     slim_batch_free(b);
     return fail(SLIM_EDEVICE, "batch: host buffer, event or stream creation failed");
@@ -426,6 +439,16 @@ int slim_batch_tune(slim_batch_t* b, void* d_ws, uint64_t ws_bytes, const slim_o
   return ok();
 }
 
+int slim_batch_stats(slim_batch_t* b, slim_stats_t* per_graph) {
+  if (!b || !per_graph) return fail(SLIM_EINVAL, "NULL argument");
+  if (!b->ran) return fail(SLIM_EINVAL, "slim_batch_stats: the batch has not run yet");
+  if (hipEventSynchronize(b->run_done) != hipSuccess ||
+      hipMemcpy(per_graph, b->dstats, sizeof(slim_stats_t) * b->count, hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return fail(SLIM_EDEVICE, "slim_batch_stats: %s", hipGetErrorString(hipGetLastError()));
+  return ok();
+}
+
 void slim_batch_free(slim_batch_t* b) {
   if (!b) return;
   drop_graph(b);
@@ -433,8 +456,13 @@ void slim_batch_free(slim_batch_t* b) {
     (void)hipEventSynchronize(b->upload_done);
     (void)hipEventDestroy(b->upload_done);
   }
+  if (b->run_done) {
+    (void)hipEventSynchronize(b->run_done);
+    (void)hipEventDestroy(b->run_done);
+  }
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->pinned) (void)hipHostFree(b->pinned);
+  if (b->dstats) (void)hipFree(b->dstats);
   delete b;
 }
 

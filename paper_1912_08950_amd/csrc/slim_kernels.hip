@@ -419,7 +419,7 @@ __device__ void tile_rows(const int64_t* row_off, int64_t j0, uint32_t lo, uint3
   __syncthreads();
   if (t == 0) L.srow[0] = lo > 0 ? lo - 1 : 0;
   __syncthreads();
-  for (uint32_t r = lo + t; r < hi; r += kBlock) {
+  for (uint64_t r = lo + (uint64_t)t; r < hi; r += kBlock) {
     const int64_t b = row_off[r], e = row_off[r + 1];
     const int64_t s = b - j0;
     if (e > b && s >= 0 && s < kTile) L.srow[s] = r;
@@ -623,7 +623,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(P p, const int64_t* 
     }
   }
   const uint32_t total = cbase[kChunks];
-  for (uint32_t r = R.lo + threadIdx.x; r < R.hi; r += kBlock) {
+  for (uint64_t r = R.lo + (uint64_t)threadIdx.x; r < R.hi; r += kBlock) {
     const int64_t s = row_off[r] - R.j0;
     uint64_t v = base + total;
     if (s >= 0 && s < (int64_t)R.span) {
@@ -693,7 +693,10 @@ __global__ void k_stats(const GDesc* gd, uint32_t count, const uint64_t* tile0,
   for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < count;
        g += gridDim.x * blockDim.x) {
     const GDesc& G = gd[g];
-    if (!G.stats) continue;
+    // gd[count] describes the union: its stats pointer, if set, is an array
+    // of one record per graph (the per-graph copy a batch keeps)
+    slim_stats_t* all = gd[count].stats;
+    if (!G.stats && !all) continue;
     const uint64_t m = G.ne / 2;
     const uint64_t m_out = (tile_base[tile0[g + 1]] - tile_base[tile0[g]]) / 2;
     const bool tr = op_lists_triangles(G.op) && counters;
@@ -704,7 +707,8 @@ __global__ void k_stats(const GDesc* gd, uint32_t count, const uint64_t* tile0,
     st.selected = tr ? counters[2 * g + 1] : 0;
     st.deleted = m - m_out;
     st.m_out = m_out;
-    *G.stats = st;
+    if (G.stats) *G.stats = st;
+    if (all) all[g] = st;
   }
 }
 

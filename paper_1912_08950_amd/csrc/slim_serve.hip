@@ -268,24 +268,33 @@ bool grow_pinned(void** p, uint64_t* have, uint64_t need) {
 int run_batch(slim_server* S, Worker& W, const std::vector<Job*>& batch) {
   hipStream_t s = W.stream;
   const uint32_t cnt = (uint32_t)batch.size();
+  // An error after the first upload was enqueued waits for the stream before
+  // it returns: the caller hands the jobs' blocks back to the arena, and a
+  // copy still in flight must not write into a block another batch reuses.
+  auto bail = [&](int rc) {
+    (void)hipStreamSynchronize(s);
+    return rc;
+  };
   std::vector<GDesc> gs(cnt);
   for (uint32_t i = 0; i < cnt; ++i) {
     Job* j = batch[i];
     const slim_job_t& J = j->spec;
     j->out_row = S->arena.alloc(8 * (J.n + 1), &j->sz_out_row);
     j->out_col = J.nnz ? S->arena.alloc(4 * J.nnz, &j->sz_out_col) : nullptr;
-    if (!j->out_row || (J.nnz && !j->out_col)) return fail(SLIM_EDEVICE, "serve: out of device memory");
+    if (!j->out_row || (J.nnz && !j->out_col))
+      return bail(fail(SLIM_EDEVICE, "serve: out of device memory"));
     const int64_t* in_row = J.row_off;
     const uint32_t* in_col = J.col;
     if (J.where == SLIM_HOST) {
       j->in_row = S->arena.alloc(8 * (J.n + 1), &j->sz_in_row);
       j->in_col = J.nnz ? S->arena.alloc(4 * J.nnz, &j->sz_in_col) : nullptr;
-      if (!j->in_row || (J.nnz && !j->in_col)) return fail(SLIM_EDEVICE, "serve: out of device memory");
+      if (!j->in_row || (J.nnz && !j->in_col))
+        return bail(fail(SLIM_EDEVICE, "serve: out of device memory"));
       if (hipMemcpyAsync(j->in_row, J.row_off, 8 * (J.n + 1), hipMemcpyHostToDevice, s) !=
               hipSuccess ||
           (J.nnz && hipMemcpyAsync(j->in_col, J.col, 4 * J.nnz, hipMemcpyHostToDevice, s) !=
                         hipSuccess))
-        return fail(SLIM_EDEVICE, "serve: input upload failed");
+        return bail(fail(SLIM_EDEVICE, "serve: input upload failed"));
       in_row = static_cast<const int64_t*>(j->in_row);
       in_col = static_cast<const uint32_t*>(j->in_col);
     }
@@ -303,13 +312,13 @@ int run_batch(slim_server* S, Worker& W, const std::vector<Job*>& batch) {
     d.out_col = static_cast<uint32_t*>(j->out_col);
   }
   SetPlan P;
-  if (int rc = plan_set(gs, P)) return rc;
+  if (int rc = plan_set(gs, P)) return bail(rc);
   const SetLayout L = set_layout(P.shape);
   const uint64_t stats_off = L.total;
   const uint64_t ws_bytes = L.total + sizeof(slim_stats_t) * cnt;
   uint64_t ws_got = 0;
   void* ws = S->arena.alloc(ws_bytes, &ws_got);
-  if (!ws) return fail(SLIM_EDEVICE, "serve: out of device memory (workspace)");
+  if (!ws) return bail(fail(SLIM_EDEVICE, "serve: out of device memory (workspace)"));
   slim_stats_t* dstats = reinterpret_cast<slim_stats_t*>(static_cast<char*>(ws) + stats_off);
   for (uint32_t i = 0; i < cnt; ++i) P.gd[i].stats = dstats + i;
   std::vector<char> hdr;

@@ -154,7 +154,7 @@ __device__ void tri_tile_rows(const int64_t* row_off, int64_t j0, uint32_t lo, u
   __syncthreads();
   if (t == 0) S.srow[0] = lo > 0 ? lo - 1 : 0;
   __syncthreads();
-  for (uint32_t r = lo + t; r < hi; r += kTB) {
+  for (uint64_t r = lo + (uint64_t)t; r < hi; r += kTB) {
     const int64_t b = row_off[r], e = row_off[r + 1];
     const int64_t s = b - j0;
     if (e > b && s >= 0 && s < kTT) S.srow[s] = r;
@@ -766,7 +766,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
       const uint32_t len = D1 - D0;
       for (uint32_t i = tid; i < len; i += kTB) S.u.dpos[i] = 0;
       __syncthreads();
-      for (uint32_t r = r_lo + tid; r <= r_hi; r += kTB) {
+      for (uint64_t r = r_lo + (uint64_t)tid; r <= r_hi; r += kTB) {
         const uint32_t fs = a.fstart[r], fe = a.fstart[r + 1];
         if (fe > fs) S.u.dpos[fs - D0] = fs - D0;
       }
@@ -1019,8 +1019,9 @@ __global__ __launch_bounds__(kListBlock) void k_eo_accept_edges(TriArgs a, uint6
     const uint32_t pend = a.fstart[vend];
     const uint32_t fs = v0 + lane < vend ? a.fstart[v0 + lane] : pend;  // row start per lane
     const uint32_t pbeg = __shfl(fs, 0, kWave);
-    for (uint32_t base = pbeg; base < pend; base += kWave) {
-      const uint32_t p = base + lane;
+    // 64-bit positions: with m near 2^32 a 32-bit base + 64 could wrap
+    for (uint64_t base = pbeg; base < pend; base += kWave) {
+      const uint64_t p = base + lane;
       uint32_t own = 0;  // last lane whose row starts at or before p
 #pragma unroll
       for (uint32_t step = kWave / 2; step > 0; step >>= 1) {
@@ -1028,7 +1029,8 @@ __global__ __launch_bounds__(kListBlock) void k_eo_accept_edges(TriArgs a, uint6
         if (__shfl(fs, (int)cand, kWave) <= p) own = cand;
       }
       if (p >= pend) continue;
-      const uint64_t mk = a.minkey[p];
+      const uint32_t pos = (uint32_t)p;  // < pend <= 2^32 - 1
+      const uint64_t mk = a.minkey[pos];
       if (mk == ~0ull) continue;
       const uint32_t v = (uint32_t)(v0 + own);
       uint32_t lo = 0, hi = a.gcount;  // the vertex's graph: last with vb <= v
@@ -1041,7 +1043,7 @@ __global__ __launch_bounds__(kListBlock) void k_eo_accept_edges(TriArgs a, uint6
       }
       const GDesc& G = a.gd[lo];
       const uint32_t vb = (uint32_t)G.vb;
-      const uint32_t rb = a.dag_col[p];
+      const uint32_t rb = a.dag_col[pos];
       const uint32_t la = v - vb, lb = a.order[rb] - vb, lw = (uint32_t)mk;
       if (!(lw > la && lw > lb)) continue;  // the edge facing the largest id decides
       const uint64_t hk = mk & 0xffffffff00000000ull;
@@ -1054,10 +1056,10 @@ __global__ __launch_bounds__(kListBlock) void k_eo_accept_edges(TriArgs a, uint6
       const uint4 wr = philox4(t0, t1, lw, 0u, G.k0, G.k1);
       const uint32_t kk = __umulhi(wr.y, 3u);
       const uint32_t p_t0w = la < lb ? p_aw : p_bw, p_t1w = la < lb ? p_bw : p_aw;
-      bit_set(a.closed, p);
+      bit_set(a.closed, pos);
       bit_set(a.closed, p_aw);
       bit_set(a.closed, p_bw);
-      bit_set(a.del, kk == 0 ? p : (kk == 1 ? p_t0w : p_t1w));
+      bit_set(a.del, kk == 0 ? pos : (kk == 1 ? p_t0w : p_t1w));
     }
   }
 }

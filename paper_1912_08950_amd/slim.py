@@ -27,13 +27,12 @@ STAT_KEYS = ("n", "m_in", "triangles", "selected", "deleted", "m_out")
 SYMBOLS = ("slim_last_error", "slim_strerror", "slim_version", "slim_load_csr",
            "slim_graph_free", "slim_workspace_size", "slim_triangle_reduce", "slim_edge_sample",
            "slim_compress", "slim_spectral_sparsify", "slim_batch_create", "slim_batch_workspace_size", "slim_batch_run", "slim_batch_set",
-           "slim_batch_get", "slim_batch_tune", "slim_batch_free",
+           "slim_batch_get", "slim_batch_tune", "slim_batch_stats", "slim_batch_free",
            "slim_serve_create", "slim_serve_submit", "slim_serve_poll", "slim_serve_wait",
            "slim_serve_next", "slim_serve_cancel", "slim_serve_copy", "slim_result_release", "slim_serve_stats",
            "slim_serve_reset_stats", "slim_serve_destroy",
            "slim_tune_set", "slim_tune_get", "slim_profile_enable", "slim_profile_read",
-           "slim_degree_kl_workspace", "slim_degree_kl", "slim_pagerank_workspace",
-           "slim_pagerank", "slim_kl_divergence_workspace", "slim_kl_divergence")
+           "slim_degree_kl_workspace", "slim_degree_kl")
 
 
 class Phase(ctypes.Structure):
@@ -131,6 +130,8 @@ def _bind(path: str = LIB_PATH):
     lib.slim_batch_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
     lib.slim_batch_tune.restype = i32
     lib.slim_batch_tune.argtypes = [vp, vp, u64, ctypes.POINTER(Out), ctypes.c_char_p, vp]
+    lib.slim_batch_stats.restype = i32
+    lib.slim_batch_stats.argtypes = [vp, vp]
     lib.slim_batch_free.restype = None
     lib.slim_batch_free.argtypes = [vp]
     lib.slim_serve_create.restype = i32
@@ -166,14 +167,6 @@ def _bind(path: str = LIB_PATH):
     lib.slim_degree_kl_workspace.argtypes = [u64, ctypes.POINTER(u64)]
     lib.slim_degree_kl.restype = i32
     lib.slim_degree_kl.argtypes = [vp, vp, u64, vp, u64, vp, vp]
-    lib.slim_pagerank_workspace.restype = i32
-    lib.slim_pagerank_workspace.argtypes = [u64, ctypes.POINTER(u64)]
-    lib.slim_pagerank.restype = i32
-    lib.slim_pagerank.argtypes = [vp, vp, u64, dbl, u32, vp, u64, vp, vp]
-    lib.slim_kl_divergence_workspace.restype = i32
-    lib.slim_kl_divergence_workspace.argtypes = [u64, ctypes.POINTER(u64)]
-    lib.slim_kl_divergence.restype = i32
-    lib.slim_kl_divergence.argtypes = [vp, vp, u64, vp, u64, vp, vp]
     return lib
 
 
@@ -367,43 +360,6 @@ def degree_kl(row_off_p, row_off_q, out=None, ws=None, stream=None):
     return out
 
 
-def pagerank(row_off, col, damping: float = 0.85, iters: int = 20, out=None, stream=None):
-    """Enqueue PageRank of the device CSR (row_off int64 [n+1], col 32-bit
-    [nnz]); returns the device float64 tensor of the n scores."""
-    n = row_off.numel() - 1
-    dev = row_off.device
-    need = ctypes.c_uint64(0)
-    _check(_lib.slim_pagerank_workspace(n, ctypes.byref(need)))
-    ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev)
-    if out is None:
-        out = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
-    with torch.cuda.device(dev):
-        rc = _lib.slim_pagerank(row_off.data_ptr(), col.data_ptr() if col.numel() else None, n,
-                                float(damping), int(iters), ws.data_ptr(), ws.numel(),
-                                out.data_ptr(), _stream_handle(stream, dev))
-    _check(rc)
-    return out[:n]
-
-
-def kl_divergence(p, q, out=None, stream=None):
-    """Enqueue D_KL(P||Q) in bits of two device float64 vectors, each
-    normalised to sum 1; returns the device float64 tensor of one element."""
-    n = p.numel()
-    if q.numel() != n:
-        raise ValueError("both vectors must have the same length")
-    dev = p.device
-    need = ctypes.c_uint64(0)
-    _check(_lib.slim_kl_divergence_workspace(n, ctypes.byref(need)))
-    ws = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
-    if out is None:
-        out = torch.empty(1, dtype=torch.float64, device=dev)
-    with torch.cuda.device(dev):
-        rc = _lib.slim_kl_divergence(p.data_ptr(), q.data_ptr(), n, ws.data_ptr(), ws.numel(),
-                                     out.data_ptr(), _stream_handle(stream, dev))
-    _check(rc)
-    return out
-
-
 def weights_numpy(bufs: Buffers):
     """Synchronise and copy the output weights of a spectral sparsification."""
     torch.cuda.synchronize(bufs.g.device)
@@ -489,8 +445,10 @@ class Batch:
                                         _stream_handle(stream, self.device)))
 
     def stats(self) -> list[dict]:
-        torch.cuda.synchronize(self.device)
-        return [dict(zip(STAT_KEYS, (int(x) for x in row))) for row in self.stats_all.cpu().numpy()]
+        """Per-graph counters of the most recent run (slim_batch_stats)."""
+        out = np.zeros((len(self.graphs), len(STAT_KEYS)), dtype=np.uint64)
+        _check(_lib.slim_batch_stats(self._h, out.ctypes.data))
+        return [dict(zip(STAT_KEYS, (int(x) for x in row))) for row in out]
 
     def result_numpy(self, i: int):
         """Synchronise and copy graph i's result: (row_off, col, stats dict)."""

@@ -59,20 +59,6 @@ def test_degree_kl_errors_without_gpu():
     assert L.slim_degree_kl(1, 1, 4, 256, 16, 8, None) == slim.ENOMEM
 
 
-def test_pagerank_and_kl_errors_without_gpu():
-    from paper_1912_08950_amd import slim
-    L = slim._lib
-    b = ctypes.c_uint64()
-    assert L.slim_pagerank_workspace(100, ctypes.byref(b)) == slim.OK and b.value >= 3 * 800
-    assert L.slim_pagerank(1, 1, 100, 1.5, 3, 256, b.value, 8, None) == slim.EINVAL  # damping
-    assert L.slim_pagerank(1, 1, 100, float("nan"), 3, 256, b.value, 8, None) == slim.EINVAL
-    assert L.slim_pagerank(1, 1, 100, 0.85, 3, 256, 16, 8, None) == slim.ENOMEM
-    assert L.slim_pagerank(None, 1, 100, 0.85, 3, 256, b.value, 8, None) == slim.EINVAL
-    assert L.slim_kl_divergence_workspace(10, ctypes.byref(b)) == slim.OK
-    assert L.slim_kl_divergence(1, 1, 10, 256, b.value, None, None) == slim.EINVAL
-    assert L.slim_kl_divergence(1, 1, 10, 256, 8, 8, None) == slim.ENOMEM
-
-
 def test_tuning_knobs():
     from paper_1912_08950_amd import slim
     for k, v in (("eo_rounds", 3), ("tri_tile", 256)):

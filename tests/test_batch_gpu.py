@@ -245,3 +245,85 @@ def test_batch_union_beyond_2_31_edges(slim):
     assert csr_digest(ro, col) == d["out_sha256"] and st["triangles"] == d["stats"]["T"]
     ro, col, st = b.result_numpy(copies - 1)
     assert st["triangles"] == d["stats"]["T"]
+
+
+def _oracle_many(graphs, jobs, slim, workers=8):
+    """Oracle results of many jobs, in threads (the C oracle runs outside the
+    GIL), in job order."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(i):
+        op, p, seed = jobs[i]
+        return oracle_run(graphs[i], "tr" if op == slim.OP_TR else "es", p, seed)
+
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(one, range(len(graphs))))
+
+
+def test_batch_full_size_range_against_oracle(slim):
+    """The batch population over its whole size range: n log-uniform in
+    [1e3, 2e5], average degree uniform in [4, 64], half G(n,q) half R-MAT,
+    plus the largest corner (n near 2e5, degree near 64) of both kinds.
+    Every job against the single-graph call (first run and replay) and the
+    oracle."""
+    graphs = (gg.batch_mix(24, 17, 1000, 200000) +
+              gg.batch_mix(2, 23, 199000, 200000, 60.0, 64.0))
+    print(f"batch full range: {len(graphs)} graphs, max n {max(g.n for g in graphs)}, "
+          f"sum m {sum(g.m for g in graphs)}", flush=True)
+    assert max(g.n for g in graphs) >= 199000
+    jobs = [(slim.OP_TR if i % 5 else slim.OP_ES, 0.5, gg.mix_seed(31, i))
+            for i in range(len(graphs))]
+    b = check_batch(slim, graphs, jobs, oracle_idx=[])
+    want = _oracle_many(graphs, jobs, slim)
+    for i, w in enumerate(want):
+        assert_same(b.result_numpy(i), w, f"oracle graph {i} {graphs[i].name}")
+
+
+def test_batch_stats_without_output_stats(slim):
+    """slim_batch_stats returns every graph's counters of the last run, also
+    when no output stats pointer was given; before a run it is refused."""
+    graphs = gg.batch_mix(6, 41, 1000, 5000) + [gg.empty(3)]
+    jobs = [((slim.OP_TR, slim.OP_ES, slim.OP_MCTR)[i % 3], 0.5, i + 1)
+            for i in range(len(graphs))]
+    dgs = [slim.Graph.from_csr(g) for g in graphs]
+    want = [single(slim, dg, *j)[2] for dg, j in zip(dgs, jobs)]
+    b = slim.Batch(dgs, jobs)
+    with pytest.raises(slim.SlimError):
+        b.stats()
+    for i in range(len(graphs)):
+        b._outs[i].stats = None
+    for _ in range(2):
+        b.run()
+        assert b.stats() == want
+
+
+def test_batch_workspace_shared_with_other_calls(slim):
+    """A batch run, then a single-graph call and another batch on the same
+    workspace (each writes its own header there), then the first batch
+    again: its replay must read its own per-graph table, not theirs."""
+    import torch
+    graphs = gg.batch_mix(8, 43, 1000, 6000)
+    jobs = [(slim.OP_TR, 0.5, gg.mix_seed(3, i)) for i in range(len(graphs))]
+    dgs = [slim.Graph.from_csr(g) for g in graphs]
+    want = [single(slim, dg, *j) for dg, j in zip(dgs, jobs)]
+    b = slim.Batch(dgs, jobs)
+    other = slim.Batch(dgs[:3], [(slim.OP_ES, 0.3, 9)] * 3)
+    ws_bytes = max(b.ws_bytes, other.ws_bytes, dgs[0].workspace_size(slim.OP_TR))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    b.ws, b.ws_bytes = ws, ws_bytes
+    other.ws, other.ws_bytes = ws, ws_bytes
+    b.run()
+    for i, w in enumerate(want):
+        assert_same(b.result_numpy(i), w, f"first run {i}")
+    bufs = slim.Buffers(dgs[0], slim.OP_TR)
+    bufs.ws, bufs.ws_bytes = ws, ws_bytes
+    slim.triangle_reduce(dgs[0], 0.9, 77, bufs)
+    other.run()
+    torch.cuda.synchronize()
+    for i in range(len(graphs)):  # poison the outputs, then replay
+        a, z = int(b.ro_base[i]), int(b.ro_base[i + 1])
+        b.row_off_all[a:z] = -1
+    b.col_all.fill_(-1)
+    b.run()
+    for i, w in enumerate(want):
+        assert_same(b.result_numpy(i), w, f"replay after shared use {i}")

@@ -712,57 +712,6 @@ def test_degree_kl_of_sampled_cycle():
     assert 0 < kl[0] < kl[1]
 
 
-# ------------------------------------------- PageRank and its divergence
-
-def test_pagerank_complete_graph_is_uniform():
-    for n in (3, 10, 57):
-        x = O.pagerank(gg.complete(n), 0.85, 20)
-        assert np.allclose(x, 1.0 / n, rtol=1e-14, atol=0)
-
-
-def test_pagerank_star_closed_form():
-    """Star with n-1 leaves: the fixed point has centre c and leaves l with
-    l = b + d c/(n-1), c = b + d (n-1) l, b = (1-d)/n, so
-    l = b (1 + d/(n-1)) / (1 - d^2)."""
-    n, d = 41, 0.85
-    b = (1 - d) / n
-    leaf = b * (1 + d / (n - 1)) / (1 - d * d)
-    centre = b + d * (n - 1) * leaf
-    x = O.pagerank(gg.star(n), d, 400)
-    assert x[0] == pytest.approx(centre, rel=1e-12)
-    assert np.allclose(x[1:], leaf, rtol=1e-12, atol=0)
-
-
-def test_pagerank_matches_linear_solve():
-    """Many steps reach the solution of (I - d M) x = (1-d)/n (M[v,u] =
-    1/deg(u) for each edge), solved directly."""
-    g = gg.er(60, 6.0, 4)
-    n, d = g.n, 0.85
-    deg = np.diff(g.row_off)
-    M = np.zeros((n, n))
-    for v in range(n):
-        for u in g.col[g.row_off[v]:g.row_off[v + 1]]:
-            M[v, u] = 1.0 / deg[u]
-    want = np.linalg.solve(np.eye(n) - d * M, np.full(n, (1 - d) / n))
-    assert np.allclose(O.pagerank(g, d, 500), want, rtol=1e-11, atol=0)
-
-
-def test_pagerank_isolated_vertex_keeps_the_base_score():
-    g = gg.from_pairs(5, [(0, 1), (1, 2), (2, 0), (2, 3)])  # vertex 4 isolated
-    x = O.pagerank(g, 0.85, 20)
-    assert x[4] == pytest.approx(0.15 / 5, rel=1e-15) and x.sum() < 1.0
-
-
-def test_vector_kl_matches_scipy_entropy():
-    from scipy.stats import entropy
-    rng = np.random.default_rng(8)
-    for _ in range(10):
-        p, q = rng.random(50) + 1e-3, rng.random(50) + 1e-3
-        assert O.kl_divergence(p, q) == pytest.approx(float(entropy(p, q, base=2)), rel=1e-12)
-    assert O.kl_divergence([1.0, 2.0], [2.0, 4.0]) == 0.0  # same distribution
-    assert O.kl_divergence([1.0, 1.0], [1.0, 0.0]) == float("inf")
-
-
 # ------------------------------------------------- spectral sparsification
 
 def _pe(g, a, b, ups):

@@ -159,3 +159,33 @@ def test_serve_completion_queue(slim):
     assert sorted(seen) == sorted(ts[1:])
     assert srv.next(0) is None
     srv.close()
+
+
+def test_serve_scale22_job_among_small_ones(slim):
+    """The serving stream's large jobs: an R-MAT scale-22 job (6.4e7 edges,
+    the 1% class of the stream) submitted between small jobs of the batch
+    population, host and device inputs; each result equals the single-graph
+    call on the same job."""
+    big = gg.rmat(22, 16, 1)
+    small = gg.batch_mix(12, 51, 1000, 20000)
+    jobs = [(g, (slim.OP_TR, slim.OP_ES, slim.OP_TR2)[i % 3], (0.2, 0.5, 0.8)[i % 3],
+             gg.mix_seed(61, i)) for i, g in enumerate(small)]
+    jobs.insert(5, (big, slim.OP_TR, 0.5, 1))
+    jobs.insert(9, (big, slim.OP_TR, 0.8, 2))
+    print(f"serve mix: {len(jobs)} jobs, big m={big.m}", flush=True)
+    dbig = slim.Graph.from_csr(big)
+    srv = slim.Server(64 << 30, n_streams=2)
+    tickets = []
+    for i, (g, op, p, seed) in enumerate(jobs):
+        src = dbig if (g is big and i == 5) else g  # one big job from device, one from host
+        tickets.append(srv.submit(src, op, p, seed))
+    for i, t in enumerate(tickets):
+        g, op, p, seed = jobs[i]
+        got = srv.result_numpy(t)
+        srv.release(t)
+        want = slim.result_numpy(slim.compress(dbig if g is big else slim.Graph.from_csr(g),
+                                               op, p, seed))
+        assert_same(got, want, f"job {i} {g.name}")
+    st = srv.stats()
+    assert st["completed"] == len(jobs) and st["failed"] == 0
+    srv.close()
