@@ -127,6 +127,26 @@ SLIM_API int slim_triangle_reduce(const slim_graph_t* g, double p, uint64_t seed
                          slim_stats_t* d_stats, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, output and errors as slim_triangle_reduce, with the workspace
+ * taken from a fixed device array of SLIM_NOALLOC_WS_BYTES (512 MiB) that
+ * the library holds on every GPU it runs on until the process ends.  The
+ * call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine); its first call on a device looks up that array's address there.
+ * A graph whose slim_workspace_size(g, SLIM_OP_TR) exceeds the array ->
+ * SLIM_ENOMEM (R-MAT scale 20, about 2^25 CSR entries, fits; scale 21 does
+ * not).  The graph must live on the current device (else SLIM_EINVAL).
+ * All calls on one GPU share that GPU's array: calls that overlap on one
+ * GPU (on different streams or threads) race and must be serialised by the
+ * caller; every call clears what it needs cleared itself.
+ */
+#define SLIM_NOALLOC_WS_BYTES (512ull << 20)
+SLIM_API int slim_triangle_reduce_noalloc(const slim_graph_t* g, double p, uint64_t seed,
+                                          int64_t* d_out_row_off, uint32_t* d_out_col,
+                                          slim_stats_t* d_stats, void* stream);
+
+/*
  * Uniform edge sampling (section 4.2.2; kernel `random_uniform`): each
  * undirected edge {a<b} is deleted independently with probability p
  * (Table `tab:theory-schemes`: (1-p)m edges remain), decided once from

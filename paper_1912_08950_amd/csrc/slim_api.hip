@@ -517,7 +517,7 @@ static_assert(sizeof(GDesc) == 120, "descriptor size");
 
 int single_op(int op, const slim_graph* g, double p, uint64_t seed, void* ws, uint64_t ws_bytes,
               int64_t* out_ro, uint32_t* out_col, float* out_w, slim_stats_t* stats,
-              hipStream_t s) {
+              hipStream_t s, bool profile = true) {
   if (!op_valid(op)) return fail(SLIM_EINVAL, "unknown op %d", op);
   const bool tr = op_lists_triangles((uint32_t)op);
   const char* what = op == SLIM_OP_TR         ? "slim_triangle_reduce"
@@ -528,15 +528,15 @@ int single_op(int op, const slim_graph* g, double p, uint64_t seed, void* ws, ui
   const uint64_t need = g && g->nnz ? set_layout(S).total : 0;
   if (int rc = check_call(g, op, p, ws, ws_bytes, need, out_ro, out_col)) return rc;
   (void)hipGetLastError();
-  prof_reset();
+  if (profile) prof_reset();
   if (g->nnz == 0) {
-    prof_begin(true, tr ? "compact" : "sample", s);
+    prof_begin(profile, tr ? "compact" : "sample", s);
     fill_i64(out_ro, g->n + 1, 0, s);
     if (stats) {
       slim_stats_t st{g->n, 0, 0, 0, 0, 0};
       put_bytes(stats, &st, sizeof(st), s);
     }
-    prof_end(true, s);
+    prof_end(profile, s);
     return hip_check(what);
   }
   Tuning knobs;
@@ -576,10 +576,37 @@ int single_op(int op, const slim_graph* g, double p, uint64_t seed, void* ws, ui
       L.t0u != offsetof(SingleHdr, t0u))
     return fail(SLIM_EDEVICE, "internal: set header layout");
   put_bytes(at<char>(ws, L.gd), &h, sizeof(h), s);
-  run_set(S, L, knobs, g->num_cu, ws, g->row_off, g->col, s, true);
+  run_set(S, L, knobs, g->num_cu, ws, g->row_off, g->col, s, profile);
   if (int rc = hip_check(what)) return rc;
   if (int rc = eo_finish(S, L, knobs, g->num_cu, ws, g->row_off, g->col, s)) return rc;
   return hip_check(what);
+}
+
+// ------------------------------------------ the entry point that allocates nothing
+// The workspace of slim_triangle_reduce_noalloc: a device array of fixed size
+// that every GPU the library runs on holds until the process ends.  In host
+// code `scratch` names only a host-side stand-in; its device address on the
+// current device comes from hipGetSymbolAddress, taken once per device and
+// kept, and only that address is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[SLIM_NOALLOC_WS_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(SLIM_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SLIM_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SLIM_OK;
 }
 
 }  // namespace
@@ -704,6 +731,28 @@ int slim_spectral_sparsify(const slim_graph_t* g, double upsilon, uint64_t seed,
                            float* d_out_weight, slim_stats_t* d_stats, void* stream) {
   return single_op(SLIM_OP_SPECTRAL, g, upsilon, seed, d_ws, ws_bytes, d_out_row_off, d_out_col,
                    d_out_weight, d_stats, static_cast<hipStream_t>(stream));
+}
+
+int slim_triangle_reduce_noalloc(const slim_graph_t* g, double p, uint64_t seed,
+                                 int64_t* d_out_row_off, uint32_t* d_out_col,
+                                 slim_stats_t* d_stats, void* stream) {
+  if (!g) return fail(SLIM_EINVAL, "graph handle is NULL");
+  if (check_p(p)) return SLIM_EINVAL;
+  const uint64_t need =
+      g->nnz ? set_layout(single_shape(g->n, g->nnz, SLIM_OP_TR)).total : 0;
+  if (need > SLIM_NOALLOC_WS_BYTES)
+    return fail(SLIM_ENOMEM,
+                "slim_triangle_reduce_noalloc: the graph needs %llu bytes of workspace, the "
+                "static workspace holds %llu (use slim_triangle_reduce with a caller workspace)",
+                (unsigned long long)need, (unsigned long long)SLIM_NOALLOC_WS_BYTES);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(SLIM_EDEVICE, "hipGetDevice failed");
+  if (dev != g->device)
+    return fail(SLIM_EINVAL, "the graph lives on device %d, current device is %d", g->device, dev);
+  void* ws = nullptr;
+  if (int rc = scratch_address(dev, &ws)) return rc;
+  return single_op(SLIM_OP_TR, g, p, seed, ws, SLIM_NOALLOC_WS_BYTES, d_out_row_off, d_out_col,
+                   nullptr, d_stats, static_cast<hipStream_t>(stream), false);
 }
 
 int slim_profile_enable(int on) {

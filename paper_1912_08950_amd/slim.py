@@ -22,10 +22,12 @@ OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, EAGAIN = 0, -1, -2, -3, -4, -5
 VALIDATE = 1
 OP_TR, OP_ES, OP_TR2, OP_MCTR, OP_SPECTRAL, OP_EOTR = 1, 2, 3, 4, 5, 6
 STAT_KEYS = ("n", "m_in", "triangles", "selected", "deleted", "m_out")
+NOALLOC_WS_BYTES = 512 << 20  # the fixed workspace of slim_triangle_reduce_noalloc
 
 # Exported symbols of libslim.so, in include/slim.h order.
 SYMBOLS = ("slim_last_error", "slim_strerror", "slim_version", "slim_load_csr",
-           "slim_graph_free", "slim_workspace_size", "slim_triangle_reduce", "slim_edge_sample",
+           "slim_graph_free", "slim_workspace_size", "slim_triangle_reduce",
+           "slim_triangle_reduce_noalloc", "slim_edge_sample",
            "slim_compress", "slim_spectral_sparsify", "slim_batch_create", "slim_batch_workspace_size", "slim_batch_run", "slim_batch_set",
            "slim_batch_get", "slim_batch_tune", "slim_batch_stats", "slim_batch_free",
            "slim_serve_create", "slim_serve_submit", "slim_serve_poll", "slim_serve_wait",
@@ -113,6 +115,8 @@ def _bind(path: str = LIB_PATH):
     for fn in (lib.slim_triangle_reduce, lib.slim_edge_sample):
         fn.restype = i32
         fn.argtypes = [vp, dbl, u64, vp, u64, vp, vp, vp, vp]
+    lib.slim_triangle_reduce_noalloc.restype = i32
+    lib.slim_triangle_reduce_noalloc.argtypes = [vp, dbl, u64, vp, vp, vp, vp]
     lib.slim_compress.restype = i32
     lib.slim_compress.argtypes = [vp, i32, dbl, u64, vp, u64, vp, vp, vp, vp]
     lib.slim_spectral_sparsify.restype = i32
