@@ -140,6 +140,85 @@ def cpu_baseline(scale):
             "seconds": round(dt, 2), "host_cpu": model, "host_threads": os.cpu_count()}
 
 
+def oracle_digest_times(names):
+    """Single-thread oracle runs at full size, as recorded when the stored
+    output digests were written (tests/golden/oracle_digests.json): seconds
+    and the input edges/s they amount to."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_digests.json")
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except OSError:
+        return {}
+    out = {}
+    for name in names:
+        e = data.get(name)
+        if not e or not e.get("oracle_seconds"):
+            continue
+        out[name] = {"seconds": e["oracle_seconds"],
+                     "edges_per_s": e["stats"]["m_in"] / e["oracle_seconds"],
+                     "cores": 1, "host_cpu": e.get("host_cpu", "unrecorded"),
+                     "graph": e["graph"], "op": e["op"], "p": e["p"]}
+    return out
+
+
+def bench_configs(args, log):
+    """The small configurations on the GPU, each against its single-thread
+    oracle time: G(2000, q = 16/1999) with Triangle p-1-Reduction and edge
+    sampling at p = 0.5 (oracle timed here), and R-MAT scale 20 with Triangle
+    p-1-Reduction at p in {0.2, 0.5, 0.8} (oracle times from the digests)."""
+    import torch
+
+    from oracle import oracle
+    from paper_1912_08950_amd import graphgen, slim
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+
+    def gpu_ms(dg, op, p, reps):
+        bufs = slim.Buffers(dg, op)
+        slim.compress(dg, op, p, 1, bufs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            slim.compress(dg, op, p, 1, bufs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        st = dict(zip(slim.STAT_KEYS, (int(x) for x in bufs.stats.cpu().numpy())))
+        return e0.elapsed_time(e1) / reps, st
+
+    out = {}
+    g1 = graphgen.er(2000, 16.0, 1)
+    d1 = slim.Graph.from_csr(g1, device=dev)
+    for name, op, ofn in (("er2000_tr_p0.5", slim.OP_TR, oracle.triangle_reduce),
+                          ("er2000_es_p0.5", slim.OP_ES, oracle.edge_sample)):
+        ms, st = gpu_ms(d1, op, 0.5, 50)
+        t0 = time.perf_counter()
+        for _ in range(5):
+            ofn(g1, 0.5, 1)
+        o_s = (time.perf_counter() - t0) / 5
+        out[name] = {"gpu_ms": ms, "gpu_edges_per_s": g1.m / (ms * 1e-3), "stats": st,
+                     "oracle_s": o_s, "oracle_edges_per_s": g1.m / o_s, "oracle_cores": 1}
+        log(f"{name}: GPU {ms:.3f} ms, oracle {o_s * 1e3:.2f} ms")
+    g2 = graphgen.rmat(20, 16, 1)
+    d2 = slim.Graph.from_csr(g2, device=dev)
+    orc = oracle_digest_times([f"rmat20_tr_p{p}" for p in (0.2, 0.5, 0.8)])
+    for p in (0.2, 0.5, 0.8):
+        name = f"rmat20_tr_p{p}"
+        ms, st = gpu_ms(d2, slim.OP_TR, p, 10)
+        out[name] = {"gpu_ms": ms, "gpu_edges_per_s": g2.m / (ms * 1e-3), "stats": st}
+        if name in orc:
+            out[name]["oracle_s"] = orc[name]["seconds"]
+            out[name]["oracle_edges_per_s"] = orc[name]["edges_per_s"]
+            out[name]["oracle_cores"] = 1
+            out[name]["oracle_host_cpu"] = orc[name]["host_cpu"]
+        log(f"{name}: GPU {ms:.3f} ms {st}")
+    del d1, d2
+    torch.cuda.empty_cache()
+    return out
+
+
 def stream_copy_gbs(stream):
     """Achievable HBM rate of a plain device copy (1 GiB read + 1 GiB written
     per launch, best of 5), the second denominator beside the published peak."""
@@ -330,6 +409,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-pool", type=int, default=256)
     ap.add_argument("--serve-streams", type=int, default=2)
+    ap.add_argument("--skip-configs", action="store_true",
+                    help="skip the G(2000, 16) and R-MAT scale-20 configurations")
     ap.add_argument("--skip-variants", action="store_true",
                     help="time Triangle p-1-Reduction only (no p-2, Min-Count, ES, spectral)")
     args = ap.parse_args()
@@ -427,7 +508,11 @@ def main():
                      "traffic": traffic, "algorithmic_bytes": tri_bytes, "kernel_ms": tri_ms,
                      "scan_items": work["sum_out_pairs"],
                      "scan_bytes_per_s": 4 * work["sum_out_pairs"] / (tri_ms * 1e-3),
-                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                     # the counter-measured HBM bytes of the same launch over its time
+                     "traffic_gbs": (traffic / (tri_ms * 1e-3) / 1e9) if traffic else None,
+                     "traffic_frac": (traffic / (tri_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+                     if traffic else None},
         "step_ms": step_ms,
         "step_ms_min_max": [min(step_ms), max(step_ms)],
         "step_algorithmic_gbs": step_bytes(g, work, stats["m_out"]) / (ms_per_step * 1e-3) / 1e9,
@@ -486,6 +571,8 @@ def main():
     result["variants"] = variants
     del bufs, es_bufs, dg
     torch.cuda.empty_cache()
+    if not args.skip_configs:
+        result["configs"] = bench_configs(args, log)
     if args.batch_count > 0:
         result["batch"] = bench_batch(args, log)
     if args.serve_rates:
@@ -495,6 +582,9 @@ def main():
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on R-MAT scale {args.cpu_scale}")
         result["cpu_baseline"] = cpu_baseline(args.cpu_scale)
+        # beside it, the oracle's own full-size runs on the benchmark graph
+        result["cpu_baseline"]["full_size_oracle"] = oracle_digest_times(
+            [f"rmat{args.scale}_{op}_p{args.p}" for op in ("tr", "tr2", "mctr", "eotr", "es")])
     print(json.dumps(result), flush=True)
 
 

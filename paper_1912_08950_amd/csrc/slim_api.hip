@@ -369,7 +369,7 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
     if (S.has_mc) {  // Min-Count: per-edge triangle counts first
       fill_u32(a.tcount, S.NNZ / 2, 0, s);
       a.pass = 0;
-      triangles(a, kModeGeneral, at<uint32_t>(ws, L.tri_ctr), num_cu, knobs.tri_blocks_per_cu,
+      triangles(a, kModeCount, at<uint32_t>(ws, L.tri_ctr), num_cu, knobs.tri_blocks_per_cu,
                 knobs.tri_chunk, s);
     }
     if (S.has_list) {

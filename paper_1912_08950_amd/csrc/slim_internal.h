@@ -137,9 +137,10 @@ struct TriArgs {
 };
 uint64_t tri_tile_max();
 // Instantiations of the triangle kernel: plain (p-1 only), general (also
-// p-2 and both Min-Count passes), Edge-Once (its bidding and acceptance
-// passes).
-constexpr int kModePlain = 0, kModeGeneral = 1, kModeEO = 2;
+// p-2 and the Min-Count selection pass), Edge-Once (its bidding passes), and
+// counting (the Min-Count counting pass: per-edge triangle counts only, no
+// selection, so hits are counted where they are found).
+constexpr int kModePlain = 0, kModeGeneral = 1, kModeEO = 2, kModeCount = 3;
 void triangles(const TriArgs& a, int mode, uint32_t* tile_ctr, int num_cu,
                int blocks_per_cu, int chunk, hipStream_t s);
 

@@ -21,10 +21,11 @@
 //
 // Variants (section 4.3), in the general instantiation of the kernel:
 // Triangle p-2-Reduction marks the two edges other than the drawn one;
-// Min-Count p-1-Reduction first runs a counting pass (every triangle adds 1
-// to each of its edges: LDS counters for (y,x) and (x,w), a global atomic
-// for (y,w)) and then marks, in each selected triangle, the edge of fewest
-// triangles (ties: the drawn index among the tied edges).
+// Min-Count p-1-Reduction first runs a counting pass (its own instantiation:
+// every triangle adds 1 to each of its edges where the probe finds it, with
+// LDS counters for (y,x) and (x,w) and a global atomic for (y,w); no queue,
+// no hash of the triple) and then marks, in each selected triangle, the edge
+// of fewest triangles (ties: the drawn index among the tied edges).
 //
 // Edge-Once p-1-Reduction (section 4.3 with the conditions of section 6.2)
 // runs in rounds.  Bids (pass 2 of this kernel): every selected triangle
@@ -382,12 +383,6 @@ __device__ __forceinline__ uint32_t tri_drain(TriCtx& C, TriSmem* Sp, const uint
     const uint32_t p_yw = ie.x + (rec.x - S.ie_pre[k]);
     const uint32_t ow = S.xold[qpos];
     const uint32_t c = ie.z, u0 = ie.w;
-    if (kGeneral && C.a.pass == 0) {  // counting pass: one more triangle on each edge
-      atomicAdd(&C.X->ie_cnt[k], 1u);
-      atomicAdd(&C.X->xcnt[qpos], 1u);
-      atomicAdd(C.a.tcount + p_yw, 1u);
-      return 0;
-    }
     uint32_t t0 = c, t1 = u0, t2 = ow;
     sort3(t0, t1, t2);  // union ids of one graph: the order of its local ids
     const uint4 wr = philox4(t0 - C.vb, t1 - C.vb, t2 - C.vb, 0u, C.k0, C.k1);
@@ -428,7 +423,7 @@ __device__ __forceinline__ uint32_t tri_drain(TriCtx& C, TriSmem* Sp, const uint
 // Process the in-edges bw[b0, b1) of the tile against the current hash.
 template <int kMode>
 __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool all_rows) {
-  constexpr bool kGeneral = kMode == kModeGeneral;
+  constexpr bool kGeneral = kMode == kModeGeneral, kCount = kMode == kModeCount;
   const int tid = threadIdx.x;
   const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const uint32_t lane = lane_id();
@@ -470,7 +465,8 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     xtag = all_rows ? (fs - C.D0) : 0u;
     S.ie[tid] = make_uint4(beg, x, c, r);
     S.ie_e[tid] = e;
-    if (kGeneral) C.X->ie_cnt[tid] = C.a.pass == 1 && C.op == SLIM_OP_MCTR ? C.a.tcount[e] : 0u;
+    if (kGeneral) C.X->ie_cnt[tid] = C.op == SLIM_OP_MCTR ? C.a.tcount[e] : 0u;
+    if (kCount) C.X->ie_cnt[tid] = 0u;
     bmp = beg;
   }
   if ((uint32_t)tid < (kBatch + 31) / 32) S.ie_flag[tid] = 0;
@@ -522,7 +518,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
   };
   fetch(kcur);
   for (uint32_t wb = ws; wb < we; wb += kWave * kUnroll) {
-    uint32_t kk[kUnroll], xb[kUnroll], wv[kUnroll];
+    uint32_t kk[kUnroll], xb[kUnroll], wv[kUnroll], ad[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const uint32_t base = wb + u * kWave;
@@ -540,7 +536,8 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
       }
       kk[u] = t < we ? k : 0xffffu;  // 0xffff: lane past the range
       xb[u] = g;
-      wv[u] = C.a.dag_col[t < we ? b + t : 0u];
+      ad[u] = t < we ? b + t : 0u;  // DAG position of the item (the edge {y,w})
+      wv[u] = C.a.dag_col[ad[u]];
     }
     // Probe window by window: the home bucket and the next one (four slots,
     // read together); a key can only sit further on if both are full.  The
@@ -574,6 +571,23 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
           }
         }
       }
+      if constexpr (kCount) {  // one more triangle on each of its three edges
+        if (hit) {
+          atomicAdd(&C.X->xcnt[qpos], 1u);
+          atomicAdd(C.a.tcount + ad[u], 1u);
+        }
+        // {y,x}: the hits of one in-edge add together (a window rarely
+        // holds more than one or two in-edges)
+        uint64_t rem = __ballot(hit);
+        while (rem) {
+          const int src = __builtin_ctzll(rem);
+          const uint32_t ks = __shfl(kk[u], src, kWave);
+          const uint64_t same = __ballot(hit && kk[u] == ks);
+          if ((int)lane == src) atomicAdd(&C.X->ie_cnt[ks], (uint32_t)__popcll(same));
+          rem &= ~same;
+        }
+        continue;
+      }
       const uint64_t bal = __ballot(hit);
       if (bal) {
         if (hit)
@@ -597,7 +611,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
   }
   __syncthreads();
   // ---- finish: (y,x) marks, or the (y,x) counts of the counting pass
-  if (kGeneral && C.a.pass == 0) {
+  if (kCount) {
     if ((uint32_t)tid < nin && C.X->ie_cnt[tid]) atomicAdd(C.a.tcount + S.ie_e[tid], C.X->ie_cnt[tid]);
   } else if ((uint32_t)tid < nin && (S.ie_flag[tid >> 5] & (1u << (tid & 31)))) {
     bit_set(C.a.del, S.ie_e[tid]);
@@ -644,12 +658,13 @@ template <int kMode>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k_triangles(
     TriArgs a, uint32_t* tile_ctr, uint32_t cap) {
   constexpr bool kGeneral = kMode == kModeGeneral, kEO = kMode == kModeEO;
-  __shared__ std::conditional_t<kGeneral, TriSmemGeneral,
+  constexpr bool kCount = kMode == kModeCount;
+  __shared__ std::conditional_t<kGeneral || kCount, TriSmemGeneral,
                                 std::conditional_t<kEO, TriSmemEO, TriSmemPlain>> SS;
   TriSmem& S = SS.s;
   TriCtx C;
   C.a = a;
-  if constexpr (kGeneral)
+  if constexpr (kGeneral || kCount)
     C.X = &SS.x;
   else
     C.X = nullptr;
@@ -701,11 +716,11 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
     // visits Min-Count graphs only, the Edge-Once passes Edge-Once graphs only
     if (!op_lists_triangles(gop)) continue;
     if (kEO ? gop != SLIM_OP_EOTR
-            : gop == SLIM_OP_EOTR || (kGeneral && a.pass == 0 && gop != SLIM_OP_MCTR))
+            : (kCount ? gop != SLIM_OP_MCTR : gop == SLIM_OP_EOTR))
       continue;
     if (R.g != gcur) {
       // the counting pass reports no triangle or selection counts
-      if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0)) tri_flush_counts(C, S, gcur);
+      if (gcur != 0xffffffffu && !kCount) tri_flush_counts(C, S, gcur);
       gcur = R.g;
       const GDesc& G = a.gd[gcur];
       C.thr = G.thr;
@@ -868,7 +883,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
       if (tid == 0 && S.bcast[3]) a.eo_live[t] = a.round;
     }
   }
-  if (gcur != 0xffffffffu && !(kGeneral && a.pass == 0)) tri_flush_counts(C, S, gcur);
+  if (gcur != 0xffffffffu && !kCount) tri_flush_counts(C, S, gcur);
   if (kEO && C.eo_append)  // the wave's unused reserved slots become dead records
     for (uint32_t i = lane; i < C.wleft; i += kWave)
       if (C.wcur + i < a.eo_cap)
@@ -1087,6 +1102,9 @@ void triangles(const TriArgs& a, int mode, uint32_t* tile_ctr, int num_cu,
   if (cap > (uint32_t)kHashCap) cap = kHashCap;
   if (mode == kModeGeneral)
     hipLaunchKernelGGL(k_triangles<kModeGeneral>, dim3((unsigned)blocks), dim3(kTB), 0, s, a,
+                       tile_ctr, cap);
+  else if (mode == kModeCount)
+    hipLaunchKernelGGL(k_triangles<kModeCount>, dim3((unsigned)blocks), dim3(kTB), 0, s, a,
                        tile_ctr, cap);
   else if (mode == kModeEO)
     hipLaunchKernelGGL(k_triangles<kModeEO>, dim3((unsigned)blocks), dim3(kTB), 0, s, a,

@@ -48,6 +48,16 @@ EO_BUCKETS = {24: 5}
 GEN_SEED, OP_SEED, EDGE_FACTOR = 1, 1, 16
 
 
+def host_cpu() -> str:
+    """CPU model of the machine running the oracle (one thread is used)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                        "unknown")
+    except OSError:
+        return "unknown"
+
+
 def csr_digest(row_off, col) -> str:
     h = hashlib.sha256()
     h.update(np.ascontiguousarray(row_off, dtype="<i8").tobytes())
@@ -94,6 +104,7 @@ def main(names):
         if w_sha is not None:
             data[name]["weights_sha256"] = w_sha
             data[name]["upsilon"] = ups
+        data[name]["host_cpu"] = host_cpu()
         if op == "eotr" and EO_BUCKETS.get(scale, 1) > 1:
             data[name]["oracle_priority_ranges"] = EO_BUCKETS[scale]
         json.dump(data, open(OUT + ".tmp", "w"), indent=1, sort_keys=True)
