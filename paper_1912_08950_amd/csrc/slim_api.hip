@@ -165,6 +165,7 @@ SetLayout set_layout(const SetShape& S) {
     L.dag_col = c.take<uint32_t>(m);
     L.eid = c.take<uint32_t>(S.NNZ);
     L.del = c.take<uint32_t>(ceil_div(m, 32) + 1);
+    L.marks = c.take<uint32_t>(ceil_div(m, 4) + 1);  // one byte per edge, filled by words
     L.counters = c.take<uint64_t>(2 * (uint64_t)S.count);
     L.sort_lists = c.take<uint32_t>(3 * n);
     L.sort_counts = c.take<uint32_t>(4);
@@ -284,7 +285,7 @@ TriArgs tri_args(const SetShape& S, const SetLayout& L, const Tuning& knobs, voi
   a.fstart = at<uint32_t>(ws, L.fstart);
   a.dag_col = at<uint32_t>(ws, L.dag_col);
   a.eid = at<uint32_t>(ws, L.eid);
-  a.del = at<uint32_t>(ws, L.del);
+  a.marks = at<uint8_t>(ws, L.marks);
   a.counters = at<uint64_t>(ws, L.counters);
   a.gd = at<GDesc>(ws, L.gd);
   a.recs = at<TileRec>(ws, L.recs_t);
@@ -345,7 +346,8 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
     const uint64_t n_t = S.n_t(knobs.tri_tile);
     tile_recs(row_off, gd, at<uint64_t>(ws, L.t0t), S.count, n_t, (uint64_t)knobs.tri_tile,
               recs_t, s);
-    fill_u32(del, ceil_div(S.NNZ / 2, 32) + 1, 0, s);
+    uint8_t* marks = at<uint8_t>(ws, L.marks);
+    fill_u32(reinterpret_cast<uint32_t*>(marks), ceil_div(S.NNZ / 2, 4) + 1, 0, s);
     fill_u32(reinterpret_cast<uint32_t*>(counters), 4 * (uint64_t)S.count, 0, s);
     prof_end(profile, s);
     prof_begin(profile, "triangles", s);
@@ -359,7 +361,7 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
     a.fstart = fstart;
     a.dag_col = dag_col;
     a.eid = eid;
-    a.del = del;
+    a.marks = marks;
     a.counters = counters;
     a.gd = gd;
     a.recs = recs_t;
@@ -389,6 +391,7 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
       prof_end(profile, s);
     }
     prof_begin(profile, "compact", s);
+    pack_marks(marks, del, S.NNZ / 2, s);
   }
   compact_out(row_off, col, eid, del, S.NNZ / 2, gd, t0c, recs_c, S.n_c, tile_cnt,
               at<uint64_t>(ws, L.masks), tile_base,
@@ -427,6 +430,7 @@ int eo_finish(const SetShape& S, const SetLayout& L, const Tuning& knobs, int nu
     const GDesc* gd = at<GDesc>(ws, L.gd);
     const uint64_t* t0c = at<uint64_t>(ws, L.t0c);
     uint64_t* tile_base = at<uint64_t>(ws, L.tile_base);
+    pack_marks(at<uint8_t>(ws, L.marks), at<uint32_t>(ws, L.del), S.NNZ / 2, s);
     compact_out(row_off, col, at<uint32_t>(ws, L.eid), at<uint32_t>(ws, L.del), S.NNZ / 2, gd,
                 t0c, at<TileRec>(ws, L.recs_c), S.n_c, at<uint32_t>(ws, L.tile_cnt),
                 at<uint64_t>(ws, L.masks), tile_base,

@@ -88,6 +88,15 @@ __device__ __forceinline__ void bit_set(uint32_t* bits, uint32_t idx) {
                         __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Deletion mark of DAG edge idx: one byte per edge, set by a plain byte
+// store.  Every store writes the same value 1 and nothing reads the bytes
+// before the marking kernels have ended, so concurrent stores to one byte
+// leave 1 in any order; stores to other bytes of the same line, from other
+// XCDs, are kept because the L2 writes back only the bytes written.  Unlike
+// an atomic OR on a bitmap word (executed past the L2, a memory transaction
+// per mark), the stores merge in the L2.
+__device__ __forceinline__ void mark_set(uint8_t* marks, uint32_t idx) { marks[idx] = 1u; }
+
 __device__ __forceinline__ bool bit_get(const uint32_t* bits, uint32_t idx) {
   return (bits[idx >> 5] >> (idx & 31u)) & 1u;
 }

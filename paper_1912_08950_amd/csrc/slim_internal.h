@@ -85,6 +85,9 @@ void dag_ranges(const uint32_t* order, const uint32_t* fstart, uint64_t n, uint2
 // edge is unmarked, ES graphs the entries whose edge is not sampled out.
 // eid/del may be NULL when the set has no TR graph.  masks: kChunks words per
 // tile (the count pass's ballots, read back by the scatter pass).
+// Packs the per-edge deletion bytes into the bitmap the compaction reads
+// (32 bytes -> one word).
+void pack_marks(const uint8_t* marks, uint32_t* del, uint64_t m, hipStream_t s);
 void compact_out(const int64_t* row_off, const uint32_t* col, const uint32_t* eid,
                  const uint32_t* del, uint64_t m, const GDesc* gd, const uint64_t* tile0,
                  const TileRec* recs, uint64_t ntiles, uint32_t* tile_cnt, uint64_t* masks,
@@ -115,7 +118,7 @@ struct TriArgs {
   const uint32_t* fstart;  // DAG row start of each union id (N+1)
   const uint32_t* dag_col;
   uint32_t* eid;           // backward CSR entries get their DAG position here
-  uint32_t* del;           // deletion bitmap over DAG positions
+  uint8_t* marks;          // deletion marks over DAG positions, one byte per edge
   uint64_t* counters;      // per graph: [2g] triangles, [2g+1] selected
   const GDesc* gd;
   const TileRec* recs;     // graph-aligned tiles of at most tri_tile_max() entries

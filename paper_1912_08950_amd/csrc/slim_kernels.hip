@@ -9,7 +9,9 @@
 //                       out in union-id row order (a stream compaction of CSR)
 //   dag_rng[n]          (begin, end) of row x of the DAG, indexed by rank id
 //   eid[nnz]            for every CSR entry of a TR graph, the DAG position of its edge
-//   del[m/32]           deletion bitmap over DAG positions
+//   marks[m]            deletion marks over DAG positions, one byte per edge
+//                       (set by the triangle kernels with byte stores)
+//   del[m/32]           the same marks packed into a bitmap for the compaction
 //   minkey[m], closed[m/32]  Edge-Once bids and closed edges over DAG positions
 #include "slim_internal.h"
 
@@ -74,6 +76,37 @@ void eo_clear_bids(uint64_t* minkey, uint32_t* closed, uint64_t m, const uint64_
   const uint64_t chunks = (m + kWave - 1) / kWave;
   hipLaunchKernelGGL(k_eo_clear_bids, dim3(grid_for(chunks * kWave)), dim3(kBlock), 0, s, minkey,
                      closed, m, eo_und, round);
+}
+
+// --------------------------------------------------------- deletion marks
+// Word i of the bitmap gets bit b set iff byte 32i + b of the marks is set;
+// each thread reads its 32 bytes as two uint4.
+__global__ __launch_bounds__(kBlock) void k_pack_marks(const uint8_t* marks, uint32_t* del,
+                                                       uint64_t m) {
+  const uint64_t words = (m + 31) / 32;
+  for (uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x; i < words;
+       i += (uint64_t)gridDim.x * kBlock) {
+    uint32_t v = 0;
+    if (32 * i + 32 <= m) {
+      const uint4* q = reinterpret_cast<const uint4*>(marks + 32 * i);
+      const uint4 a = q[0], b = q[1];
+      const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if ((w[k] >> (8 * t)) & 0xffu) v |= 1u << (4 * k + t);
+    } else {
+      for (uint64_t e = 32 * i; e < m; ++e)
+        if (marks[e]) v |= 1u << (e - 32 * i);
+    }
+    del[i] = v;
+  }
+}
+
+void pack_marks(const uint8_t* marks, uint32_t* del, uint64_t m, hipStream_t s) {
+  if (m) hipLaunchKernelGGL(k_pack_marks, dim3(grid_for((m + 31) / 32)), dim3(kBlock), 0, s, marks,
+                            del, m);
 }
 
 // ------------------------------------------------------------------- scan

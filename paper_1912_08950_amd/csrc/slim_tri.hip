@@ -15,9 +15,10 @@
 // (Philox4x32-10 of the id-sorted triple) 64 at a time.
 //
 // Deletion marks: (x,w) lies in the tile's own out-lists and is collected
-// in an LDS bitmap; (y,x) is a per-in-edge flag; (y,w) is an atomic OR into
-// the global bitmap over DAG positions.  All marks are idempotent ORs, so
-// the result does not depend on the order in which triangles are found.
+// in an LDS bitmap; (y,x) is a per-in-edge flag; (y,w) is a byte store into
+// the global per-edge mark bytes over DAG positions (the first two are
+// flushed there too).  Every mark sets a value to 1 and nothing is cleared,
+// so the result does not depend on the order in which triangles are found.
 //
 // Variants (section 4.3), in the general instantiation of the kernel:
 // Triangle p-2-Reduction marks the two edges other than the drawn one;
@@ -247,11 +248,8 @@ __device__ void tri_flush_xbits(TriCtx& C, TriSmem& S) {
   } else {
     const uint32_t nwords = (C.D0 % 32 + C.hlen + 31) / 32;
     const uint32_t base = C.D0 / 32;
-    for (uint32_t i = threadIdx.x; i < nwords; i += kTB) {
-      const uint32_t v = S.xbits[i];
-      if (v)
-        __hip_atomic_fetch_or(C.a.del + base + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    for (uint32_t i = threadIdx.x; i < nwords; i += kTB)
+      for (uint32_t v = S.xbits[i]; v; v &= v - 1) mark_set(C.a.marks, (base + i) * 32u + __builtin_ctz(v));
   }
   __syncthreads();
 }
@@ -274,7 +272,7 @@ __device__ void tri_forward_eids(TriCtx& C, TriSmem& S, uint32_t ia, uint32_t ib
 
 // Marks the edge of triangle (y,x,w) that does not contain vertex `excl`
 // (union ids: c = y, u0 = x, ow = w).
-__device__ __forceinline__ void tri_mark(uint32_t* del, TriSmem& S, uint32_t excl, uint32_t c,
+__device__ __forceinline__ void tri_mark(uint8_t* marks, TriSmem& S, uint32_t excl, uint32_t c,
                                          uint32_t ow, uint32_t k, uint32_t qpos, uint32_t D0,
                                          uint32_t p_yw) {
   if (excl == ow) {  // edge {y,x}: flag of the in-edge
@@ -282,8 +280,8 @@ __device__ __forceinline__ void tri_mark(uint32_t* del, TriSmem& S, uint32_t exc
   } else if (excl == c) {  // edge {x,w}: position qpos of the hashed range
     const uint32_t bit = D0 % 32 + qpos;
     atomicOr(&S.xbits[bit >> 5], 1u << (bit & 31));
-  } else {  // edge {y,w}: global bitmap (no return value: nothing waits on it)
-    bit_set(del, p_yw);
+  } else {  // edge {y,w}: a byte store (nothing waits on it)
+    mark_set(marks, p_yw);
   }
 }
 
@@ -392,7 +390,7 @@ __device__ __forceinline__ uint32_t tri_drain(TriCtx& C, TriSmem* Sp, const uint
       // edge e of ({t0,t1}, {t0,t2}, {t1,t2}) is the one without excl[e]
       const uint32_t excl[3] = {t2, t1, t0};
       if constexpr (!kGeneral) {
-        tri_mark(C.a.del, S, excl[__umulhi(w1, 3u)], c, ow, k, qpos, C.D0, p_yw);
+        tri_mark(C.a.marks, S, excl[__umulhi(w1, 3u)], c, ow, k, qpos, C.D0, p_yw);
       } else if (C.op == SLIM_OP_MCTR) {
         uint32_t t[3];
 #pragma unroll
@@ -407,13 +405,13 @@ __device__ __forceinline__ uint32_t tri_drain(TriCtx& C, TriSmem* Sp, const uint
           if (pick == 0) break;
           --pick;
         }
-        tri_mark(C.a.del, S, excl[e], c, ow, k, qpos, C.D0, p_yw);
+        tri_mark(C.a.marks, S, excl[e], c, ow, k, qpos, C.D0, p_yw);
       } else {
         const uint32_t kk = __umulhi(w1, 3u);
 #pragma unroll
         for (int e = 0; e < 3; ++e)
           if ((C.op == SLIM_OP_TR2) ? (uint32_t)e != kk : (uint32_t)e == kk)
-            tri_mark(C.a.del, S, excl[e], c, ow, k, qpos, C.D0, p_yw);
+            tri_mark(C.a.marks, S, excl[e], c, ow, k, qpos, C.D0, p_yw);
       }
     }
   }
@@ -614,7 +612,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
   if (kCount) {
     if ((uint32_t)tid < nin && C.X->ie_cnt[tid]) atomicAdd(C.a.tcount + S.ie_e[tid], C.X->ie_cnt[tid]);
   } else if ((uint32_t)tid < nin && (S.ie_flag[tid >> 5] & (1u << (tid & 31)))) {
-    bit_set(C.a.del, S.ie_e[tid]);
+    mark_set(C.a.marks, S.ie_e[tid]);
   }
   if (C.ie_key && (uint32_t)tid < nin && C.ie_key[tid] != ~0ull)  // the batch's {y,x} bids
     eo_bid(C.a.minkey + S.ie_e[tid], C.ie_key[tid]);
@@ -995,7 +993,7 @@ __global__ __launch_bounds__(kListBlock) void k_eo_list_accept(TriArgs a) {
     bit_set(a.closed, r0.x);
     bit_set(a.closed, r0.y);
     bit_set(a.closed, r0.z);
-    bit_set(a.del, r0.w);
+    mark_set(a.marks, r0.w);
   }
 }
 
@@ -1074,7 +1072,7 @@ __global__ __launch_bounds__(kListBlock) void k_eo_accept_edges(TriArgs a, uint6
       bit_set(a.closed, pos);
       bit_set(a.closed, p_aw);
       bit_set(a.closed, p_bw);
-      bit_set(a.del, kk == 0 ? pos : (kk == 1 ? p_t0w : p_t1w));
+      mark_set(a.marks, kk == 0 ? pos : (kk == 1 ? p_t0w : p_t1w));
     }
   }
 }
