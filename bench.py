@@ -166,7 +166,8 @@ def bench_configs(args, log):
     """The small configurations on the GPU, each against its single-thread
     oracle time: G(2000, q = 16/1999) with Triangle p-1-Reduction and edge
     sampling at p = 0.5 (oracle timed here), and R-MAT scale 20 with Triangle
-    p-1-Reduction at p in {0.2, 0.5, 0.8} (oracle times from the digests)."""
+    p-1-Reduction at p in {0.2, 0.5, 0.8} (oracle times from the digests);
+    and the single-call time of the serving stream's R-MAT scale-22 job."""
     import torch
 
     from oracle import oracle
@@ -214,7 +215,15 @@ def bench_configs(args, log):
             out[name]["oracle_cores"] = 1
             out[name]["oracle_host_cpu"] = orc[name]["host_cpu"]
         log(f"{name}: GPU {ms:.3f} ms {st}")
-    del d1, d2
+    # the large jobs of the serving stream: R-MAT scale 22 at each p it uses
+    g3 = graphgen.rmat(22, 16, 3)
+    d3 = slim.Graph.from_csr(g3, device=dev)
+    for p in (0.2, 0.5, 0.8):
+        name = f"rmat22_serve_job_tr_p{p}"
+        ms, st = gpu_ms(d3, slim.OP_TR, p, 5)
+        out[name] = {"gpu_ms": ms, "gpu_edges_per_s": g3.m / (ms * 1e-3), "stats": st}
+        log(f"{name}: GPU {ms:.3f} ms")
+    del d1, d2, d3
     torch.cuda.empty_cache()
     return out
 
