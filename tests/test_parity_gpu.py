@@ -331,6 +331,13 @@ def test_rmat24_mctr_full(slim, rmat24):
     _check_digest(slim, rmat24, "rmat24_mctr_p0.5")
 
 
+def test_rmat24_eotr_full(slim, rmat24):
+    """R-MAT scale 24: Edge-Once p-1-Reduction (its parallel rounds) against
+    the oracle's stored digest of the priority-order walk (taken in pieces
+    of the priority range to fit host memory)."""
+    _check_digest(slim, rmat24, "rmat24_eotr_p0.5")
+
+
 
 # ------------------------------- Triangle p-2 and Min-Count p-1 variants
 
