@@ -56,9 +56,10 @@ __device__ __forceinline__ uint4 philox4(uint32_t x0, uint32_t x1, uint32_t x2, 
     // one 32x32->64 product each (a single multiply-add instruction on gfx950)
     const uint64_t a = (uint64_t)0xD2511F53u * x0;
     const uint64_t b = (uint64_t)0xCD9E8D57u * x2;
-    x0 = (uint32_t)(b >> 32) ^ x1 ^ k0;
+    // three-input exclusive or (truth table 0x96) in one instruction
+    x0 = __builtin_amdgcn_bitop3_b32((uint32_t)(b >> 32), x1, k0, 0x96);
     x1 = (uint32_t)b;
-    x2 = (uint32_t)(a >> 32) ^ x3 ^ k1;
+    x2 = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), x3, k1, 0x96);
     x3 = (uint32_t)a;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;

@@ -77,7 +77,7 @@ struct TriSmem {
   uint32_t cmax[kTC];
   uint16_t bw[kTT];    // local indices of the tile's backward entries, in order
   uint32_t fwd[kTT / 32];  // forward entries of the tile (edge ids come from the hash)
-  uint4 hb[kBuckets];         // two slots {w, tag}; tag = (position in range << 16) | row offset
+  uint4 hb[kBuckets + 1];     // two slots {w, tag}; tag = (position in range << 16) | row offset
   uint32_t xold[kHashCap];    // original id of each hashed out-list entry
   uint32_t xbits[kHashCap / 32 + 2];
   uint4 ie[kBatch];           // {scan begin, x rank, y old id, x old id}
@@ -118,9 +118,15 @@ struct TriSmemEO {
   uint64_t ie_key[kBatch];
 };
 
+// Home bucket of key (w, row offset xb), below kBuckets.
 __device__ __forceinline__ uint32_t hbucket(uint32_t w, uint32_t xb) {
-  return ((w ^ (xb * 0x85EBCA6Bu)) * 0x9E3779B1u) >> (32 - kBucketBits);
+  return ((w * 0x9E3779B1u) >> (32 - kBucketBits)) ^ (xb & (kBuckets - 1));
 }
+
+// Probe order: home buckets are 0 .. kBuckets-1; the walk goes on to the
+// spare bucket kBuckets and then wraps to 0, so a home bucket and the next
+// one are always adjacent in LDS.
+__device__ __forceinline__ uint32_t hnext(uint32_t b) { return b == kBuckets ? 0u : b + 1u; }
 
 // Look up (w, row offset xb) starting at bucket b.  Slots fill in probe
 // order and are never removed, so a bucket with a free slot ends the probe.
@@ -138,7 +144,7 @@ __device__ __forceinline__ bool hlookup(const uint4* hb, uint32_t w, uint32_t xb
       return true;
     }
     if (e.z == kEmpty) return false;
-    b = (b + 1) & (kBuckets - 1);
+    b = hnext(b);
   }
 }
 
@@ -205,7 +211,7 @@ struct TriCtx {
 // Hash the out-list entries [D0, D0 + len) under key (w, row start offset);
 // the offset comes from dpos (all rows of the tile) or is 0 (one row).
 __device__ void tri_build_hash(TriCtx& C, TriSmem& S, uint32_t len, bool use_dpos) {
-  for (int i = threadIdx.x; i < kBuckets; i += kTB)
+  for (int i = threadIdx.x; i < kBuckets + 1; i += kTB)
     S.hb[i] = make_uint4(kEmpty, 0u, kEmpty, 0u);
   for (int i = threadIdx.x; i < kHashCap / 32 + 2; i += kTB) S.xbits[i] = 0;
   __syncthreads();
@@ -228,7 +234,7 @@ __device__ void tri_build_hash(TriCtx& C, TriSmem& S, uint32_t len, bool use_dpo
         hw[4 * b + 3] = (q << 16) | xb;
         break;
       }
-      b = (b + 1) & (kBuckets - 1);
+      b = hnext(b);
     }
     // counts exist only for Min-Count graphs: loaded for their selection
     // pass, zeroed for their counting pass (other operations never read them)
@@ -532,42 +538,54 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
         b = after ? c_bmp : b;
         g = after ? c_tag : g;
       }
-      kk[u] = t < we ? k : 0xffffu;  // 0xffff: lane past the range
-      xb[u] = g;
+      // a lane past the range gets row offset 0xffff, which no hashed entry
+      // has (offsets are below kHashCap): it never hits
+      kk[u] = k;
+      xb[u] = t < we ? g : 0xffffu;
       ad[u] = t < we ? b + t : 0u;  // DAG position of the item (the edge {y,w})
       wv[u] = C.a.dag_col[ad[u]];
     }
     // Probe window by window: the home bucket and the next one (four slots,
     // read together); a key can only sit further on if both are full.  The
-    // scan is bound by the latency of the dag_col loads, so the registers go
-    // to keeping many windows' loads in flight, not to batching the probes.
+    // SIMDs issue vector instructions in most cycles of this loop, so the
+    // probe is written for few of them: one compare per slot key, the row
+    // tag of the first slot holding w, and the rare cases (the same w in
+    // another row of the tile, two full buckets) as divergent branches,
+    // which the exec mask skips when no lane takes them.
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const uint32_t bku = hbucket(wv[u], xb[u]);
       const uint4 e = S.hb[bku];
-      const uint4 f = S.hb[(bku + 1) & (kBuckets - 1)];
+      const uint4 f = S.hb[bku + 1];  // adjacent: the spare bucket follows the last
       const uint32_t t = wb + u * kWave + lane, wq = wv[u], g = xb[u];
-      const bool valid = kk[u] != 0xffffu;
-      const bool m0 = (e.x == wq) & ((e.y & 0xffffu) == g);
-      const bool m1 = (e.z == wq) & ((e.w & 0xffffu) == g);
-      const bool m2 = (f.x == wq) & ((f.y & 0xffffu) == g);
-      const bool m3 = (f.z == wq) & ((f.w & 0xffffu) == g);
-      bool hit = valid & (m0 | m1 | m2 | m3);
-      uint32_t qpos = (m0 ? e.y : m1 ? e.w : m2 ? f.y : f.w) >> 16;
-      bool more = valid & !(m0 | m1 | m2 | m3) & (e.z != kEmpty) & (f.z != kEmpty);
-      uint32_t bkt = (bku + 1) & (kBuckets - 1);
-      if (__ballot(more)) {  // both buckets full: keep probing (rare)
-        while (__ballot(more)) {
-          if (more) {
-            bkt = (bkt + 1) & (kBuckets - 1);
-            const uint4 h = S.hb[bkt];
-            const bool n0 = (h.x == wq) & ((h.y & 0xffffu) == g);
-            const bool n1 = (h.z == wq) & ((h.w & 0xffffu) == g);
-            hit = n0 | n1;
-            qpos = (n0 ? h.y : h.w) >> 16;
-            more = !(n0 | n1) & (h.z != kEmpty);
-          }
-        }
+      const bool k0 = e.x == wq, k1 = e.z == wq, k2 = f.x == wq;
+      uint32_t tsel = f.w;
+      tsel = k2 ? f.y : tsel;
+      tsel = k1 ? e.w : tsel;
+      tsel = k0 ? e.y : tsel;
+      const bool kany = (k0 | k1 | k2) || f.z == wq;
+      const bool rowok = (tsel & 0xffffu) == g;
+      bool hit = kany & rowok;
+      uint32_t qpos = tsel >> 16;
+      bool more = !kany & (e.z != kEmpty) & (f.z != kEmpty);
+      if (kany & !hit) {  // w is hashed for another row too: check all four slots
+        const bool m0 = k0 & ((e.y & 0xffffu) == g);
+        const bool m1 = k1 & ((e.w & 0xffffu) == g);
+        const bool m2 = k2 & ((f.y & 0xffffu) == g);
+        const bool m3 = (f.z == wq) & ((f.w & 0xffffu) == g);
+        hit = m0 | m1 | m2 | m3;
+        qpos = (m0 ? e.y : m1 ? e.w : m2 ? f.y : f.w) >> 16;
+        more = !hit & (e.z != kEmpty) & (f.z != kEmpty);
+      }
+      uint32_t bkt = bku + 1;
+      while (more) {  // both buckets full: keep probing (rare)
+        bkt = hnext(bkt);
+        const uint4 h = S.hb[bkt];
+        const bool n0 = (h.x == wq) & ((h.y & 0xffffu) == g);
+        const bool n1 = (h.z == wq) & ((h.w & 0xffffu) == g);
+        hit = n0 | n1;
+        qpos = (n0 ? h.y : h.w) >> 16;
+        more = !(n0 | n1) & (h.z != kEmpty);
       }
       if constexpr (kCount) {  // one more triangle on each of its three edges
         if (hit) {
@@ -586,11 +604,11 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
         }
         continue;
       }
-      const uint64_t bal = __ballot(hit);
+      const uint64_t bal = __builtin_amdgcn_ballot_w64(hit);
       if (bal) {
-        if (hit)
-          q[(qhead + qcnt + __popcll(bal & lanemask_lt())) % kQ] =
-              make_uint2(t, (kk[u] << 16) | qpos);
+        const uint32_t before = __builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (hit) q[(qhead + qcnt + before) % kQ] = make_uint2(t, (kk[u] << 16) | qpos);
         qcnt += __popcll(bal);
         if (qcnt >= (uint32_t)kWave) {
           wave_sync();
