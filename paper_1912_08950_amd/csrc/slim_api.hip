@@ -163,6 +163,7 @@ SetLayout set_layout(const SetShape& S) {
     L.fstart = c.take<uint32_t>(n + 1);
     L.dag_rng = c.take<uint2>(n);
     L.dag_col = c.take<uint32_t>(m);
+    L.fence = c.take<uint32_t>(ceil_div(m, kFenceStep) + 1);
     L.eid = c.take<uint32_t>(S.NNZ);
     L.del = c.take<uint32_t>(ceil_div(m, 32) + 1);
     L.marks = c.take<uint32_t>(ceil_div(m, 4) + 1);  // one byte per edge, filled by words
@@ -284,6 +285,7 @@ TriArgs tri_args(const SetShape& S, const SetLayout& L, const Tuning& knobs, voi
   a.dag_rng = at<uint2>(ws, L.dag_rng);
   a.fstart = at<uint32_t>(ws, L.fstart);
   a.dag_col = at<uint32_t>(ws, L.dag_col);
+  a.fence = at<uint32_t>(ws, L.fence);
   a.eid = at<uint32_t>(ws, L.eid);
   a.marks = at<uint8_t>(ws, L.marks);
   a.counters = at<uint64_t>(ws, L.counters);
@@ -339,6 +341,8 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
     dag_ranges(order, fstart, S.N, dag_rng, s);
     sort_rows(dag_rng, S.N, dag_col, at<uint32_t>(ws, L.sort_lists),
               at<uint32_t>(ws, L.sort_counts), num_cu, s);
+    uint32_t* fence = at<uint32_t>(ws, L.fence);
+    fence_samples(dag_col, S.NNZ / 2, fence, s);
     eid = at<uint32_t>(ws, L.eid);
     del = at<uint32_t>(ws, L.del);
     counters = at<uint64_t>(ws, L.counters);
@@ -360,6 +364,7 @@ void run_set(const SetShape& S, const SetLayout& L, const Tuning& knobs, int num
     a.dag_rng = dag_rng;
     a.fstart = fstart;
     a.dag_col = dag_col;
+    a.fence = fence;
     a.eid = eid;
     a.marks = marks;
     a.counters = counters;

@@ -44,7 +44,7 @@ struct SetLayout {
   uint64_t recs_c, recs_u, recs_t;
   uint64_t tile_cnt, tile_base, scan_tmp, masks;
   uint64_t ka, va, kb, vb, rank, rcol, hist, hist_scan;
-  uint64_t fstart, dag_rng, dag_col, eid, del, marks, counters;
+  uint64_t fstart, dag_rng, dag_col, fence, eid, del, marks, counters;
   uint64_t sort_lists, sort_counts, tri_ctr, tcount;
   uint64_t minkey, closed, eo_und, eo_live, eo_list, eo_misc;
   uint64_t total;

@@ -106,6 +106,11 @@ void validate_entries(const int64_t* row_off, const uint32_t* col, uint64_t n,
 constexpr uint32_t kSortMin = 32;
 void sort_rows(const uint2* dag_rng, uint64_t n, uint32_t* dag_col, uint32_t* lists,
                uint32_t* counts, int num_cu, hipStream_t s);
+// fence[q] = dag_col[kFenceStep * q]: the first rank id of every 128-byte
+// line of the sorted DAG columns, so that a search for a rank id in a DAG
+// row reads the row's samples and then a single line of dag_col.
+constexpr uint32_t kFenceStep = 32;
+void fence_samples(const uint32_t* dag_col, uint64_t m, uint32_t* fence, hipStream_t s);
 
 // Triangle listing + selection + deletion marks (slim_tri.hip).
 struct TriArgs {
@@ -117,6 +122,7 @@ struct TriArgs {
   const uint2* dag_rng;    // DAG row of each rank id
   const uint32_t* fstart;  // DAG row start of each union id (N+1)
   const uint32_t* dag_col;
+  const uint32_t* fence;   // dag_col[kFenceStep * q] for every q
   uint32_t* eid;           // backward CSR entries get their DAG position here
   uint8_t* marks;          // deletion marks over DAG positions, one byte per edge
   uint64_t* counters;      // per graph: [2g] triangles, [2g+1] selected

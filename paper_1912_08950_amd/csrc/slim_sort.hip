@@ -170,6 +170,22 @@ __global__ __launch_bounds__(1024) void k_sort_huge(const uint2* dag_rng, uint32
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_fence(const uint32_t* dag_col, uint64_t m,
+                                                  uint32_t* fence) {
+  const uint64_t nq = (m + kFenceStep - 1) / kFenceStep;
+  for (uint64_t q = blockIdx.x * (uint64_t)kBlock + threadIdx.x; q < nq;
+       q += (uint64_t)gridDim.x * kBlock)
+    fence[q] = dag_col[q * kFenceStep];
+}
+
+void fence_samples(const uint32_t* dag_col, uint64_t m, uint32_t* fence, hipStream_t s) {
+  const uint64_t nq = (m + kFenceStep - 1) / kFenceStep;
+  if (nq == 0) return;
+  uint64_t g = (nq + kBlock - 1) / kBlock;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_fence, dim3((unsigned)g), dim3(kBlock), 0, s, dag_col, m, fence);
+}
+
 void sort_rows(const uint2* dag_rng, uint64_t n, uint32_t* dag_col, uint32_t* lists,
                uint32_t* counts, int num_cu, hipStream_t s) {
   fill_u32(counts, 4, 0, s);

@@ -148,6 +148,40 @@ __device__ __forceinline__ bool hlookup(const uint4* hb, uint32_t w, uint32_t xb
   }
 }
 
+// First position in the sorted DAG range [lo, hi) whose rank id is >= x
+// (the entry x itself in a valid input; hi if every entry is below x).  The
+// fence samples of the line starts inside the range pick the one 128-byte
+// line of dag_col that holds the answer, and the halving ends inside it: a
+// search of a long row reads its samples (one or two lines) and one line of
+// dag_col, instead of a new line for each of its first halvings.
+__device__ __forceinline__ uint32_t dag_find(const TriArgs& a, uint32_t lo, uint32_t hi,
+                                             uint32_t x) {
+  static_assert(kFenceStep == 32, "line starts are multiples of 32 positions");
+  // line starts 32q inside [lo, hi): q in [qa, qe)
+  const uint32_t qa = (lo >> 5) + ((lo & 31u) != 0), qe = (hi >> 5) + ((hi & 31u) != 0);
+  if (qa < qe) {
+    uint32_t l = qa, h = qe;  // first q whose line starts above x
+    while (l < h) {
+      const uint32_t mid = l + ((h - l) >> 1);
+      if (a.fence[mid] <= x)
+        l = mid + 1;
+      else
+        h = mid;
+    }
+    if (l > qa) lo = (l - 1) << 5;  // the line of the last start at or below x
+    const uint64_t lend = (uint64_t)l << 5;
+    if (lend < hi) hi = (uint32_t)lend;
+  }
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (a.dag_col[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -450,15 +484,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
       e = C.a.eid[j];
       closed = bit_get(C.a.closed, e);
     } else {
-      uint32_t lo = yr.x, hi = yr.y;
-      while (lo < hi) {
-        const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (C.a.dag_col[mid] < x)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      e = lo;  // dag_col[e] == x
+      e = dag_find(C.a, yr.x, yr.y, x);  // dag_col[e] == x
       C.a.eid[j] = e;
     }
     // out(x) empty: no triangle, no scan (e == yr.y only for inputs that
@@ -1027,14 +1053,7 @@ __global__ __launch_bounds__(kListBlock) void k_eo_list_accept(TriArgs a) {
 __device__ __forceinline__ uint32_t dag_pos(const TriArgs& a, uint32_t ru, uint32_t rv) {
   const uint32_t lo_r = ru < rv ? ru : rv, hi_r = ru < rv ? rv : ru;
   const uint2 rg = a.dag_rng[lo_r];
-  uint32_t lo = rg.x, hi = rg.y;
-  while (lo < hi) {
-    const uint32_t mid = lo + ((hi - lo) >> 1);
-    if (a.dag_col[mid] < hi_r)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
+  const uint32_t lo = dag_find(a, rg.x, rg.y, hi_r);
   return lo < rg.y && a.dag_col[lo] == hi_r ? lo : kDead;
 }
 
