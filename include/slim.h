@@ -422,6 +422,12 @@ SLIM_API void slim_serve_destroy(slim_server_t* s);
  *   "tri_tile"           CSR entries per triangle work tile: 256, 512 or 1024
  *   "eo_rounds"          Edge-Once rounds enqueued before the host checks
  *                        whether more are needed, 1..64 (default 16)
+ *   "eo_list_try"        Edge-Once: a bidding round also writes its undecided
+ *                        triangles to a list (later rounds run on the list)
+ *                        once the previous round's undecided count is at most
+ *                        this percent of the list capacity (three triangles
+ *                        per edge); a list that overflows is dropped and the
+ *                        next round tries again.  0..100000 (default 250)
  * Unknown key or value out of range -> SLIM_EINVAL.
  */
 SLIM_API int slim_tune_set(const char* key, int64_t value);

@@ -261,10 +261,13 @@ void eo_rounds(const SetShape& S, const SetLayout& L, const Tuning& knobs, int n
   a.eo_list_cnt = at<uint64_t>(ws, L.eo_misc);
   a.eo_state = reinterpret_cast<uint32_t*>(at<uint64_t>(ws, L.eo_misc) + 2);
   a.eo_cap = kEoListPerEdge * (S.NNZ / 2);
+  a.eo_list_try = (uint32_t)knobs.eo_list_try;
   a.gcount = S.count;
   for (uint32_t r = r0; r <= r1; ++r) {
-    eo_clear_bids(a.minkey, a.closed, S.NNZ / 2, a.eo_und, r, s);
     a.round = r;
+    eo_round_start(a, s);
+    eo_clear_bids(a.minkey, a.closed, S.NNZ / 2, a.eo_und, a.eo_state, a.eo_list_cnt, r, s);
+    eo_list_clear(a, num_cu, s);
     a.pass = 2;
     triangles(a, kModeEO, at<uint32_t>(ws, L.tri_ctr), num_cu, knobs.tri_blocks_per_cu,
               knobs.tri_chunk, s);
@@ -462,6 +465,9 @@ bool tune_apply(Tuning& t, const char* key, int64_t value) {
   } else if (k == "eo_rounds") {
     if (value < 1 || value > 64) return false;
     t.eo_rounds = (int)value;
+  } else if (k == "eo_list_try") {
+    if (value < 0 || value > 100000) return false;
+    t.eo_list_try = (int)value;
   } else {
     return false;
   }
@@ -478,6 +484,8 @@ bool tune_read(const Tuning& t, const char* key, int64_t* value) {
     *value = t.tri_tile;
   else if (k == "eo_rounds")
     *value = t.eo_rounds;
+  else if (k == "eo_list_try")
+    *value = t.eo_list_try;
   else
     return false;
   return true;

@@ -143,6 +143,7 @@ struct TriArgs {
   uint32_t pass;           // 0: Min-Count counting, 1: selection and marks,
                            // 2: Edge-Once bids
   uint32_t round;          // Edge-Once round (1, 2, ...)
+  uint32_t eo_list_try;    // Edge-Once: Tuning::eo_list_try
 };
 uint64_t tri_tile_max();
 // Instantiations of the triangle kernel: plain (p-1 only), general (also
@@ -169,18 +170,32 @@ __host__ __device__ inline bool op_valid(int op) {
 // counter array (the rounds of greedy parallel maximal independent set with
 // random priorities grow as log of the triangle count).
 constexpr uint32_t kEoMaxRounds = 1024;
-// Capacity of each Edge-Once list in triangles per DAG edge.  The bidding
-// pass starts the list once the undecided triangles fit (R-MAT graphs keep
-// about a third of them per round, so three per edge saves two listing
-// passes over one per edge); later rounds copy the survivors from one list
-// into the other, so their cost falls with the undecided count.  The two
-// lists take 2 * 32 * kEoListPerEdge bytes of workspace per edge.
+// Capacity of each Edge-Once list in triangles per DAG edge.  A bidding
+// pass tries to start the list once the previous round's undecided count is
+// at most Tuning::eo_list_try percent of the capacity (R-MAT graphs keep
+// about a third to two fifths of them per round); if its own bidders
+// overflow the list, the round accepts by the edge-parallel kernel and the
+// next round may list again.
+// Later rounds copy the survivors from one list into the other, so their
+// cost falls with the undecided count.  The two lists take
+// 2 * 32 * kEoListPerEdge bytes of workspace per edge.
 constexpr uint64_t kEoListPerEdge = 3;
+// A list round clears the previous round's bids through that round's list
+// records when there are at most this many (three random stores each),
+// instead of sweeping every edge.
+constexpr uint64_t kEoListClearMax = 1ull << 23;
 void eo_clear_bids(uint64_t* minkey, uint32_t* closed, uint64_t m, const uint64_t* eo_und,
-                   uint32_t round, hipStream_t s);
+                   const uint32_t* eo_state, const uint64_t* eo_list_cnt, uint32_t round,
+                   hipStream_t s);
 // Acceptance of round a.round by an edge-parallel kernel over the n union
 // vertices (returns at once once the triangles are listed).
 void eo_accept_edges(const TriArgs& a, uint64_t n, int num_cu, hipStream_t s);
+// Start of round a.round: a list that the previous round started but
+// overflowed is dropped (the round accepted by the edge-parallel kernel).
+void eo_round_start(const TriArgs& a, hipStream_t s);
+// Clears the bids of the previous round through its list records, when the
+// round runs on the lists and they are few (k_eo_clear_bids sweeps otherwise).
+void eo_list_clear(const TriArgs& a, int num_cu, hipStream_t s);
 // Bids and acceptance of round a.round on the triangle lists (both return
 // at once unless the list was started in an earlier round; acceptance also
 // in the listing round).  Round r after the listing round L bids from list
@@ -195,6 +210,8 @@ struct Tuning {
   int tri_blocks_per_cu = 2;  // resident blocks of the triangle kernel per CU
   int tri_tile = 1024;        // CSR entries per triangle tile (a power of two, 256..1024)
   int eo_rounds = 16;         // Edge-Once rounds enqueued before the host checks (1..64)
+  int eo_list_try = 250;      // Edge-Once: list from a round whose previous undecided count is
+                              //   at most this percent of the list capacity (0..100000)
 };
 Tuning& tuning();
 // Checks a knob value; returns false if `key` is unknown or out of range.

@@ -50,8 +50,16 @@ void fill_i64(int64_t* p, uint64_t len, int64_t v, hipStream_t s) {
 // selected triangle on it is decided); then every bid is reset.  A wave
 // takes 64 edges, so the two bitmap words of its chunk are its own.
 __global__ void k_eo_clear_bids(uint64_t* minkey, uint32_t* closed, uint64_t m,
-                                const uint64_t* eo_und, uint32_t round) {
+                                const uint64_t* eo_und, const uint32_t* eo_state,
+                                const uint64_t* eo_list_cnt, uint32_t round) {
   if (round > 1 && eo_und[round - 1] == 0) return;  // the rounds have ended
+  // a round on the lists whose previous bidders are few clears their bids
+  // through their list records (k_eo_list_clear); every edge of an
+  // undecided triangle got a bid then, so closing unbid edges is moot
+  const uint32_t listed = eo_state[0];
+  if (listed != 0 && listed < round &&
+      eo_list_cnt[(round - listed - 1) & 1u] <= kEoListClearMax)
+    return;
   const uint32_t lane = lane_id();
   const uint64_t waves = (uint64_t)gridDim.x * kWavesPerBlock;
   for (uint64_t c = blockIdx.x * (uint64_t)kWavesPerBlock + threadIdx.x / kWave;
@@ -71,11 +79,12 @@ __global__ void k_eo_clear_bids(uint64_t* minkey, uint32_t* closed, uint64_t m,
 }
 
 void eo_clear_bids(uint64_t* minkey, uint32_t* closed, uint64_t m, const uint64_t* eo_und,
-                   uint32_t round, hipStream_t s) {
+                   const uint32_t* eo_state, const uint64_t* eo_list_cnt, uint32_t round,
+                   hipStream_t s) {
   if (!m) return;
   const uint64_t chunks = (m + kWave - 1) / kWave;
   hipLaunchKernelGGL(k_eo_clear_bids, dim3(grid_for(chunks * kWave)), dim3(kBlock), 0, s, minkey,
-                     closed, m, eo_und, round);
+                     closed, m, eo_und, eo_state, eo_list_cnt, round);
 }
 
 // --------------------------------------------------------- deletion marks

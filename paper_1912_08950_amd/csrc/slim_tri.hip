@@ -724,21 +724,24 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
   C.eo_append = false;
   // Edge-Once rounds end once a bidding pass finds no undecided triangle:
   // bids of round r stop if round r-1 had none, acceptance if round r has
-  // none.  Once the undecided triangles fit the list (round r-1 had at most
-  // its capacity), the bidding pass of round r also lists them, and later
-  // rounds run on the list instead of listing triangles again.
+  // none.  Once the undecided triangles may fit the list (round r-1 had at
+  // most eo_list_try percent of its capacity), the bidding pass of round r also
+  // lists them; if they fit, later rounds run on the list instead of listing
+  // triangles again, else the list is dropped at the start of round r+1.
   if (kEO) {
     if (a.round > 1 && a.eo_und[a.round - 1] == 0) return;
     const uint32_t listed = a.eo_state[0];
     if (listed != 0 && listed < a.round) return;
     // every wave may leave up to achunk reserved slots unused (marked dead
-    // at the end), so listing starts only when they fit beside the triangles
+    // at the end); they count against the capacity like the triangles
     const uint64_t waves = (uint64_t)gridDim.x * kTW;
     const uint64_t ch = a.eo_cap / (8 * waves);
     C.achunk = (uint32_t)(ch < 256 ? ch : 256);
     C.wcur = 0;
     C.wleft = 0;
-    C.eo_append = a.round >= 2 && a.eo_und[a.round - 1] + waves * C.achunk <= a.eo_cap;
+    // (another block of this pass may already have recorded the round)
+    C.eo_append = a.round >= 2 && (listed == 0 || listed == a.round) &&
+                  a.eo_und[a.round - 1] * 100 <= (uint64_t)a.eo_list_try * a.eo_cap;
     if (C.eo_append && threadIdx.x == 0) a.eo_state[0] = a.round;
   }
   const int tid = threadIdx.x, w = tid / kWave;
@@ -941,11 +944,49 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
 // round's bidders.
 constexpr int kListBlock = 256;
 
+// The listing round's bidders did not fit the list (the slots taken,
+// unused reserved ones included, pass its capacity).
+__device__ __forceinline__ bool eo_list_overflow(const TriArgs& a) {
+  return a.eo_list_cnt[0] > a.eo_cap;
+}
+
 // Bids on the list start the round after the listing round, acceptance on
-// the list in the listing round itself.
+// the list in the listing round itself (unless the list overflowed).
 __device__ __forceinline__ bool eo_listed_round(const TriArgs& a, bool accept) {
   const uint32_t listed = a.eo_state[0];
-  return listed != 0 && (listed < a.round || (accept && listed == a.round));
+  return listed != 0 &&
+         (listed < a.round || (accept && listed == a.round && !eo_list_overflow(a)));
+}
+
+__global__ void k_eo_round_start(TriArgs a) {
+  const uint32_t listed = a.eo_state[0];
+  if (listed != 0 && listed + 1 == a.round && eo_list_overflow(a)) {
+    a.eo_state[0] = 0;
+    a.eo_list_cnt[0] = 0;
+    a.eo_list_cnt[1] = 0;
+  }
+}
+
+// Clears the bids that the previous round's bidders placed: they are the
+// records of the list this round bids from (all of them bid on their three
+// edges; a dead slot of the listing round's list bid nowhere).
+__global__ __launch_bounds__(kListBlock) void k_eo_list_clear(TriArgs a) {
+  if (a.eo_und[a.round - 1] == 0) return;
+  const uint32_t listed = a.eo_state[0];
+  if (listed == 0 || listed >= a.round) return;
+  const uint32_t src = (a.round - listed - 1) & 1u;
+  uint64_t n = a.eo_list_cnt[src];
+  if (n > kEoListClearMax) return;  // k_eo_clear_bids swept every edge
+  if (n > a.eo_cap) n = a.eo_cap;
+  const uint4* list = a.eo_list + (uint64_t)src * 2 * a.eo_cap;
+  for (uint64_t i = blockIdx.x * (uint64_t)kListBlock + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kListBlock) {
+    const uint4 r0 = list[2 * i];
+    if (r0.x == kDead) continue;
+    a.minkey[r0.x] = ~0ull;
+    a.minkey[r0.y] = ~0ull;
+    a.minkey[r0.z] = ~0ull;
+  }
 }
 
 // Records a wave takes at a time: it counts the ones that will bid, reserves
@@ -1059,7 +1100,9 @@ __device__ __forceinline__ uint32_t dag_pos(const TriArgs& a, uint32_t ru, uint3
 
 __global__ __launch_bounds__(kListBlock) void k_eo_accept_edges(TriArgs a, uint64_t n) {
   const uint32_t listed = a.eo_state[0];
-  if ((listed != 0 && listed <= a.round) || a.eo_und[a.round] == 0) return;
+  const bool on_list = listed != 0 && listed <= a.round &&
+                       !(listed == a.round && eo_list_overflow(a));
+  if (on_list || a.eo_und[a.round] == 0) return;
   const uint32_t lane = lane_id();
   const uint64_t waves = (uint64_t)gridDim.x * (kListBlock / kWave);
   for (uint64_t g = blockIdx.x * (uint64_t)(kListBlock / kWave) + threadIdx.x / kWave;
@@ -1117,6 +1160,15 @@ __global__ __launch_bounds__(kListBlock) void k_eo_accept_edges(TriArgs a, uint6
 void eo_accept_edges(const TriArgs& a, uint64_t n, int num_cu, hipStream_t s) {
   const unsigned blocks = (unsigned)(num_cu > 0 ? num_cu * 8 : 2048);
   hipLaunchKernelGGL(k_eo_accept_edges, dim3(blocks), dim3(kListBlock), 0, s, a, n);
+}
+
+void eo_round_start(const TriArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_eo_round_start, dim3(1), dim3(1), 0, s, a);
+}
+
+void eo_list_clear(const TriArgs& a, int num_cu, hipStream_t s) {
+  const unsigned blocks = (unsigned)(num_cu > 0 ? num_cu * 8 : 2048);
+  hipLaunchKernelGGL(k_eo_list_clear, dim3(blocks), dim3(kListBlock), 0, s, a);
 }
 
 void eo_list_round(const TriArgs& a, int num_cu, hipStream_t s) {

@@ -61,13 +61,16 @@ def test_degree_kl_errors_without_gpu():
 
 def test_tuning_knobs():
     from paper_1912_08950_amd import slim
-    for k, v in (("eo_rounds", 3), ("tri_tile", 256)):
+    for k, v in (("eo_rounds", 3), ("tri_tile", 256), ("eo_list_try", 0), ("eo_list_try", 100000)):
         old = slim.tune_get(k)
         slim.tune_set(k, v)
         assert slim.tune_get(k) == v
         slim.tune_set(k, old)
     with pytest.raises(slim.SlimError):
         slim.tune_set("eo_rounds", 0)
+    with pytest.raises(slim.SlimError):
+        slim.tune_set("eo_list_try", 100001)
+    assert slim.tune_get("eo_list_try") == 250
     old = slim.tune_get("tri_chunk")
     slim.tune_set("tri_chunk", 64)
     assert slim.tune_get("tri_chunk") == 64

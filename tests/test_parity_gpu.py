@@ -395,6 +395,24 @@ def test_variants_schedule_independence(slim, knobs):
             slim.tune_set(k, v)
 
 
+@pytest.mark.parametrize("try_pct", [0, 100000])
+def test_edge_once_list_start_and_overflow(slim, try_pct):
+    """Edge-Once with the triangle list never started (0) and started as
+    early as possible (100000: the second round already tries; on these
+    graphs its bidders overflow the list, which is then dropped, and the
+    third round lists again).  K_120 keeps 51,650 of its 168,128 selected
+    triangles undecided after the first round against a list of 21,420, the
+    R-MAT s16 graph 2.86e6 against 2.73e6."""
+    old = slim.tune_get("eo_list_try")
+    try:
+        slim.tune_set("eo_list_try", try_pct)
+        for g in (gg.complete(120), gg.rmat(16, 16, 1), gg.rmat(13, 16, 2)):
+            assert_same(gpu_run_op(slim, g, "eotr", 0.6, 4), oracle_run_x(g, "eotr", 0.6, 4),
+                        f"{g.name} eo_list_try={try_pct}")
+    finally:
+        slim.tune_set("eo_list_try", old)
+
+
 # ------------------------------------------------- spectral sparsification
 
 def oracle_spectral(g, ups, seed):
