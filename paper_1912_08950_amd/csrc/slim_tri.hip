@@ -53,10 +53,15 @@
 
 namespace slim {
 
-constexpr int kTB = 512;             // threads per block
+#ifndef SLIM_TRI_BLOCK
+#define SLIM_TRI_BLOCK 512
+#endif
+constexpr int kTB = SLIM_TRI_BLOCK;  // threads per block
 constexpr int kTW = kTB / kWave;     // waves per block
 constexpr int kTT = 1024;            // CSR entries per tile
 constexpr int kTC = kTT / kWave;     // 64-entry chunks per tile
+constexpr int kChunksPerWave = (kTC + kTW - 1) / kTW;
+constexpr int kWavesPerEU = 2 * kTW / 4;  // two resident blocks per CU (LDS), four SIMDs
 constexpr int kHashCap = 2048;       // out-list entries hashed per pass
 constexpr int kBuckets = 2048;       // hash buckets of two slots (load <= 1/2)
 constexpr int kBucketBits = 11;
@@ -697,7 +702,7 @@ __device__ void tri_flush_counts(TriCtx& C, TriSmem& S, uint32_t g) {
 // graph of a block's tiles never decreases: counts are flushed when it
 // changes and at the end.
 template <int kMode>
-__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k_triangles(
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kWavesPerEU))) void k_triangles(
     TriArgs a, uint32_t* tile_ctr, uint32_t cap) {
   constexpr bool kGeneral = kMode == kModeGeneral, kEO = kMode == kModeEO;
   constexpr bool kCount = kMode == kModeCount;
@@ -784,8 +789,9 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
     tri_tile_rows(a.row_off, j0, R.lo, R.hi, S);
     // ---- backward entries (the in-edges of the tile's rows), in CSR order
     uint32_t fb = 0;
-    for (int k = 0; k < kTC / kTW; ++k) {
+    for (int k = 0; k < kChunksPerWave; ++k) {
       const int c = w + k * kTW;
+      if (c >= kTC) break;
       const uint32_t i = c * kWave + lane;
       bool f = false, g = false;
       if (i < span) {
@@ -810,7 +816,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4))) void k
       if (lane == kWave - 1) S.bcast[1] = (uint32_t)incl;
     }
     __syncthreads();
-    for (int k = 0; k < kTC / kTW; ++k) {
+    for (int k = 0; k < kChunksPerWave; ++k) {
       if (fb & (1u << k)) {
         const int c = w + k * kTW;
         S.bw[S.cbase[c] + __popcll(S.cmask[c] & lanemask_lt())] = (uint16_t)(c * kWave + lane);
