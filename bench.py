@@ -48,10 +48,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def stored_traffic(path):
-    """HBM bytes per launch of the triangle kernel from a committed rocprofv3
-    summary ("hbm_bytes_per_launch:" line), if it was taken on the current
-    kernel sources ("kernel_source_sha256:" line); else None."""
+def stored_counter(path, key):
+    """A per-launch figure of the triangle kernel from a committed rocprofv3
+    summary ("hbm_bytes_per_launch:", "valu_wave_instructions_per_launch:"),
+    if the summary was taken on the current kernel sources
+    ("kernel_source_sha256:" line); else None."""
     if not os.path.exists(path):
         return None
     kv = {}
@@ -63,9 +64,26 @@ def stored_traffic(path):
     if kv.get("kernel_source_sha256") != kernel_source_hash():
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+def stored_traffic(path):
+    """HBM bytes per launch of the triangle kernel (None if not current)."""
+    return stored_counter(path, "hbm_bytes_per_launch")
+
+
+def valu_issue(kernel_ms):
+    """Time the triangle kernel's SIMDs spend issuing its VALU instructions
+    (a wave64 instruction takes four cycles of a 16-lane SIMD; 256 CUs x 4
+    SIMDs at 2.4 GHz), from the stored counter; None if it is not current."""
+    v = stored_counter(os.path.join(ROOT, "profiles", "k_triangles_rmat24.txt"),
+                       "valu_wave_instructions_per_launch")
+    if v is None:
+        return None
+    issue_ms = v * 4 / (256 * 4 * 2.4e9) * 1e3
+    return {"wave_instructions": v, "issue_ms": issue_ms, "issue_frac": issue_ms / kernel_ms}
 
 
 def copy_calibration():
@@ -533,7 +551,11 @@ def main():
                      # the counter-measured HBM bytes of the same launch over its time
                      "traffic_gbs": (traffic / (tri_ms * 1e-3) / 1e9) if traffic else None,
                      "traffic_frac": (traffic / (tri_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
-                     if traffic else None},
+                     if traffic else None,
+                     # vector-instruction issue: wave64 VALU instructions of the
+                     # launch (SQ_INSTS_VALU, stored profile) at four cycles each
+                     # on 1024 SIMDs at the nominal 2.4 GHz, against the launch
+                     "valu": valu_issue(tri_ms)},
         "step_ms": step_ms,
         "step_ms_min_max": [min(step_ms), max(step_ms)],
         "step_algorithmic_gbs": step_bytes(g, work, stats["m_out"]) / (ms_per_step * 1e-3) / 1e9,
