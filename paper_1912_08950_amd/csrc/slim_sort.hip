@@ -3,14 +3,16 @@
 // The triangle kernel finds the in-neighbour edge (y,x) inside out(y) by
 // binary search and scans only the part of out(y) ranked above x, which is
 // the suffix of a sorted row.  Rows of length 2..kSortMin are sorted by one
-// thread each (insertion sort in a private LDS slice), up to 256 by one
-// wave, up to 4096 by one block in LDS, longer rows by one block in global
-// memory.
+// thread each (insertion sort in a private LDS slice), up to 2048 by one
+// wave in registers (a bitonic network over 64 lanes x E values: pairs
+// within a lane are exchanged in registers, pairs across lanes by a lane
+// shuffle, so no LDS traffic and no barrier), up to 4096 by one block in
+// LDS, longer rows by one block in global memory.
 #include "slim_internal.h"
 
 namespace slim {
 
-constexpr uint32_t kWaveSortMax = 256;
+constexpr uint32_t kWaveSortMax = 2048;
 constexpr uint32_t kBlockSortMax = 4096;
 constexpr uint32_t kPad = 0xffffffffu;  // larger than every rank id (n <= 2^32-1)
 
@@ -73,41 +75,81 @@ __global__ __launch_bounds__(kBlock) void k_sort_classify(const uint2* dag_rng, 
   }
 }
 
-// One wave per row (kSortMin < len <= 256): bitonic sort in a 1 KB LDS slice.
+// Bitonic sort of one row of len <= 64 * E entries in the registers of one
+// wave: element i = lane * E + r sits in register r of its lane, padded with
+// kPad past len.  Step (k, j) pairs i with i ^ j; the lower index of the pair
+// keeps the minimum where (i & k) == 0, the maximum elsewhere.
+template <int E>
+__device__ __forceinline__ void wave_sort_regs(uint32_t* row, uint32_t len) {
+  const uint32_t lane = lane_id();
+  uint32_t v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const uint32_t i = lane * E + r;
+    v[r] = i < len ? row[i] : kPad;
+  }
+#pragma unroll
+  for (uint32_t k = 2; k <= 64u * E; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      if (j < (uint32_t)E) {  // the pair is in this lane: registers r and r | j
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          if ((r & j) != 0) continue;
+          const bool up = ((lane * E + r) & k) == 0;
+          const uint32_t a = v[r], b = v[r | j];
+          const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+          v[r] = up ? lo : hi;
+          v[r | j] = up ? hi : lo;
+        }
+      } else {  // the partner is register r of lane ^ (j / E)
+        const uint32_t lj = j / E;
+        const bool lower = (lane & lj) == 0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const bool up = ((lane * E + r) & k) == 0;
+          const uint32_t o = __shfl_xor(v[r], (int)lj, kWave);
+          const uint32_t lo = v[r] < o ? v[r] : o, hi = v[r] < o ? o : v[r];
+          v[r] = lower == up ? lo : hi;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const uint32_t i = lane * E + r;
+    if (i < len) row[i] = v[r];
+  }
+}
+
+// One wave per row (kSortMin < len <= 2048): the register sort with the
+// fewest values per lane that holds the row.
 __global__ __launch_bounds__(kBlock) void k_sort_wave(const uint2* dag_rng, uint32_t* dag_col,
                                                       const uint32_t* list,
                                                       const uint32_t* count) {
-  __shared__ uint32_t buf[kWavesPerBlock][kWaveSortMax];
-  const int w = threadIdx.x / kWave, lane = lane_id();
-  uint32_t* s = buf[w];
+  const int w = threadIdx.x / kWave;
   const uint32_t total = *count;
   for (uint32_t i = blockIdx.x * kWavesPerBlock + w; i < total;
        i += gridDim.x * kWavesPerBlock) {
     const uint2 r = dag_rng[list[i]];
-    const uint32_t len = r.y - r.x, P = pow2_ceil(len);
-    for (uint32_t k = lane; k < P; k += kWave) s[k] = k < len ? dag_col[r.x + k] : kPad;
-    wave_sync_lds();
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        for (uint32_t t = lane; t < P / 2; t += kWave) {
-          const uint32_t a = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // lower index of the pair
-          const uint32_t b = a | j;
-          const bool up = (a & k) == 0;
-          const uint32_t va = s[a], vb = s[b];
-          if ((va > vb) == up) {
-            s[a] = vb;
-            s[b] = va;
-          }
-        }
-        wave_sync_lds();
-      }
-    }
-    for (uint32_t k = lane; k < len; k += kWave) dag_col[r.x + k] = s[k];
-    wave_sync_lds();
+    const uint32_t len = r.y - r.x;
+    uint32_t* row = dag_col + r.x;
+    if (len <= 64)
+      wave_sort_regs<1>(row, len);
+    else if (len <= 128)
+      wave_sort_regs<2>(row, len);
+    else if (len <= 256)
+      wave_sort_regs<4>(row, len);
+    else if (len <= 512)
+      wave_sort_regs<8>(row, len);
+    else if (len <= 1024)
+      wave_sort_regs<16>(row, len);
+    else
+      wave_sort_regs<32>(row, len);
   }
 }
 
-// One block per row (256 < len <= 4096): bitonic sort in LDS.
+// One block per row (2048 < len <= 4096): bitonic sort in LDS.
 __global__ __launch_bounds__(kBlock) void k_sort_block(const uint2* dag_rng, uint32_t* dag_col,
                                                        const uint32_t* list,
                                                        const uint32_t* count) {
