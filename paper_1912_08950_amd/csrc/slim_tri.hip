@@ -117,10 +117,12 @@ struct TriSmemGeneral {
   TriX x;
 };
 // LDS of the Edge-Once instantiation: the smallest bid on each in-edge of
-// the batch, written to the global minimum once per batch.
+// the batch, written to the global minimum once per batch, and the smallest
+// priority word bid on each hashed out-list entry in the current pass.
 struct TriSmemEO {
   TriSmem s;
   uint64_t ie_key[kBatch];
+  uint32_t xmin[kHashCap];
 };
 
 // Home bucket of key (w, row offset xb), below kBuckets.
@@ -232,6 +234,7 @@ struct TriCtx {
   TriArgs a;
   TriX* X;        // general instantiation only
   uint64_t* ie_key;  // Edge-Once instantiation only
+  uint32_t* xmin;    // Edge-Once instantiation only
   uint32_t cap;   // out-list entries hashed per pass (<= kHashCap)
   int64_t j0;
   uint32_t D0;    // first DAG position of the hashed range
@@ -259,6 +262,7 @@ __device__ void tri_build_hash(TriCtx& C, TriSmem& S, uint32_t len, bool use_dpo
   for (uint32_t q = threadIdx.x; q < len; q += kTB) {
     const uint32_t w = C.a.dag_col[C.D0 + q];
     S.xold[q] = C.a.order[w];
+    if (C.xmin) C.xmin[q] = 0xffffffffu;
     // Edge-Once rounds after the first pass: a closed edge {x,w} decides
     // every triangle on it, so it is left out of the hash
     if (skip_closed && bit_get(C.a.closed, C.D0 + q)) continue;
@@ -371,7 +375,10 @@ __device__ __forceinline__ uint32_t tri_drain_eo(TriCtx& C, TriSmem& S, const ui
       const uint32_t kk = __umulhi(wr.y, 3u);  // edge kk of ({t0,t1}, {t0,t2}, {t1,t2})
       const uint32_t excl = kk == 0 ? t2 : (kk == 1 ? t1 : t0);
       atomicMin((unsigned long long*)&C.ie_key[k], (unsigned long long)k_yx);  // LDS
-      eo_bid(mk + e_xw, k_xw);
+      // {x,w} lies in the hashed range: a bid whose priority word is above
+      // the smallest one this pass has bid on the entry cannot hold the
+      // minimum (that one went to the global key), so only the others bid
+      if (wr.z <= atomicMin(&C.xmin[qpos], wr.z)) eo_bid(mk + e_xw, k_xw);
       eo_bid(mk + p_yw, k_yw);
       res = 1;
       app = true;
@@ -715,10 +722,13 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     C.X = &SS.x;
   else
     C.X = nullptr;
-  if constexpr (kEO)
+  if constexpr (kEO) {
     C.ie_key = SS.ie_key;
-  else
+    C.xmin = SS.xmin;
+  } else {
     C.ie_key = nullptr;
+    C.xmin = nullptr;
+  }
   C.cap = cap;
   C.op = 0;
   C.n_tri = 0;
