@@ -67,6 +67,26 @@ def bipartite_plus_matching(a, b):
     return gg.from_pairs(a + b, pairs, f"K{a},{b}+M")
 
 
+def sort_classes(lengths=(2, 31, 32, 33, 64, 65, 128, 129, 256, 257, 512, 513, 1024, 1025,
+                           2048, 2049)):
+    """DAG rows of given lengths: hubs 0..H-1 on a path, each with H+1
+    private leaves (so every hub outranks every other vertex), and one vertex
+    per length L joined to hubs 0..L-1, whose DAG row is exactly those L
+    hubs. Vertex L's triangles are its L-1 consecutive hub pairs; a mis-sorted
+    row would misplace its in-edge searches and its suffix scans."""
+    H = max(lengths)
+    pairs = [(h, h + 1) for h in range(H - 1)]
+    nxt = H
+    for L in lengths:
+        pairs += [(nxt, h) for h in range(L)]
+        nxt += 1
+    for h in range(H):
+        pairs += [(h, nxt + i) for i in range(H + 1)]
+        nxt += H + 1
+    g = gg.from_pairs(nxt, pairs, "sort_classes")
+    return g
+
+
 SMALL = {
     "K3": lambda: gg.complete(3),
     "K4": lambda: gg.complete(4),
@@ -411,6 +431,16 @@ def test_edge_once_list_start_and_overflow(slim, try_pct):
                         f"{g.name} eo_list_try={try_pct}")
     finally:
         slim.tune_set("eo_list_try", old)
+
+
+@pytest.mark.parametrize("p", [1.0, 0.5])
+def test_dag_rows_of_every_sort_class(slim, p):
+    """Rows of 2 to 2049 entries cover the thread, wave-register (64 x 1 to
+    64 x 32 values) and block sorts and their boundaries."""
+    g = sort_classes()
+    for op in ("tr",):
+        assert_same(gpu_run(slim, g, op, p, 3), oracle_run(g, op, p, 3), f"sort classes {op} p={p}")
+    assert_same(gpu_run_op(slim, g, "eotr", p, 3), oracle_run_x(g, "eotr", p, 3), "sort classes eotr")
 
 
 # ------------------------------------------------- spectral sparsification
