@@ -82,7 +82,7 @@ struct TriSmem {
   uint32_t cmax[kTC];
   uint16_t bw[kTT];    // local indices of the tile's backward entries, in order
   uint32_t fwd[kTT / 32];  // forward entries of the tile (edge ids come from the hash)
-  uint4 hb[kBuckets + 1];     // two slots {w, tag}; tag = (position in range << 16) | row offset
+  uint4 hb[kBuckets + 1];     // two slots {w, tag}; tag = (position in range << 16) | row tag
   uint32_t xold[kHashCap];    // original id of each hashed out-list entry
   uint32_t xbits[kHashCap / 32 + 2];
   uint4 ie[kBatch];           // {scan begin, x rank, y old id, x old id}
@@ -125,32 +125,50 @@ struct TriSmemEO {
   uint32_t xmin[kHashCap];
 };
 
-// Home bucket of key (w, row offset xb), below kBuckets.
-__device__ __forceinline__ uint32_t hbucket(uint32_t w, uint32_t xb) {
-  return ((w * 0x9E3779B1u) >> (32 - kBucketBits)) ^ (xb & (kBuckets - 1));
+// A key is (w, row tag) with row tag = 16 x (offset of the row's start in
+// the hashed range), below 2^15; bucket addresses are byte offsets (16 B per
+// bucket).  A slot's tag word holds (position in range << 16) | row tag, and
+// bit 31 of a bucket's second tag word (kPassed) is set once an insertion
+// found the bucket full and went on past it.
+constexpr uint32_t kRowTag = 4;             // row tag = row offset << kRowTag
+constexpr uint32_t kPassed = 0x80000000u;
+constexpr uint32_t kQposMask = 0x7fffu;     // position in range, from tag >> 16
+constexpr uint32_t kNoRow = 0xffffu;        // a row tag no key has
+
+// Byte offset of the home bucket of key (w, row tag g), below 16 kBuckets:
+// bits 21..31 of w * 0x9E3779B1 xor the row offset, times 16.
+__device__ __forceinline__ uint32_t hhome(uint32_t w, uint32_t g) {
+  return (((w * 0x9E3779B1u) >> (32 - kBucketBits - kRowTag)) ^ g) &
+         ((kBuckets - 1) << kRowTag);
 }
 
 // Probe order: home buckets are 0 .. kBuckets-1; the walk goes on to the
 // spare bucket kBuckets and then wraps to 0, so a home bucket and the next
-// one are always adjacent in LDS.
-__device__ __forceinline__ uint32_t hnext(uint32_t b) { return b == kBuckets ? 0u : b + 1u; }
+// one are always adjacent in LDS.  b is a byte offset.
+__device__ __forceinline__ uint32_t hnext(uint32_t b) {
+  return b == (kBuckets << kRowTag) ? 0u : b + (1u << kRowTag);
+}
 
-// Look up (w, row offset xb) starting at bucket b.  Slots fill in probe
-// order and are never removed, so a bucket with a free slot ends the probe.
-__device__ __forceinline__ bool hlookup(const uint4* hb, uint32_t w, uint32_t xb,
+__device__ __forceinline__ uint4 hread(const uint4* hb, uint32_t b) {
+  return *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(hb) + b);
+}
+
+// Look up (w, row tag g).  Slots fill in probe order and are never removed,
+// so the key lies past a bucket only if an insertion went on past it.
+__device__ __forceinline__ bool hlookup(const uint4* hb, uint32_t w, uint32_t g,
                                         uint32_t& qpos) {
-  uint32_t b = hbucket(w, xb);
+  uint32_t b = hhome(w, g);
   for (;;) {
-    const uint4 e = hb[b];
-    if (e.x == w && (e.y & 0xffffu) == xb) {
-      qpos = e.y >> 16;
+    const uint4 e = hread(hb, b);
+    if (e.x == w && (e.y & 0xffffu) == g) {
+      qpos = (e.y >> 16) & kQposMask;
       return true;
     }
-    if (e.z == w && (e.w & 0xffffu) == xb) {
-      qpos = e.w >> 16;
+    if (e.z == w && (e.w & 0xffffu) == g) {
+      qpos = (e.w >> 16) & kQposMask;
       return true;
     }
-    if (e.z == kEmpty) return false;
+    if (!(e.w & kPassed)) return false;
     b = hnext(b);
   }
 }
@@ -250,8 +268,8 @@ struct TriCtx {
   uint64_t n_tri, n_sel;
 };
 
-// Hash the out-list entries [D0, D0 + len) under key (w, row start offset);
-// the offset comes from dpos (all rows of the tile) or is 0 (one row).
+// Hash the out-list entries [D0, D0 + len) under key (w, row tag); the row
+// start offset comes from dpos (all rows of the tile) or is 0 (one row).
 __device__ void tri_build_hash(TriCtx& C, TriSmem& S, uint32_t len, bool use_dpos) {
   for (int i = threadIdx.x; i < kBuckets + 1; i += kTB)
     S.hb[i] = make_uint4(kEmpty, 0u, kEmpty, 0u);
@@ -266,17 +284,21 @@ __device__ void tri_build_hash(TriCtx& C, TriSmem& S, uint32_t len, bool use_dpo
     // Edge-Once rounds after the first pass: a closed edge {x,w} decides
     // every triangle on it, so it is left out of the hash
     if (skip_closed && bit_get(C.a.closed, C.D0 + q)) continue;
-    const uint32_t xb = use_dpos ? S.u.dpos[q] : 0u;
-    uint32_t b = hbucket(w, xb);
+    const uint32_t g = (use_dpos ? S.u.dpos[q] : 0u) << kRowTag;
+    uint32_t b = hhome(w, g);
     for (;;) {
-      if (atomicCAS(&hw[4 * b], kEmpty, w) == kEmpty) {
-        hw[4 * b + 1] = (q << 16) | xb;
+      uint32_t* s = hw + b / 4;
+      // tags are ORed in: an insertion passing the bucket may set kPassed
+      // in the second tag word at the same time
+      if (atomicCAS(&s[0], kEmpty, w) == kEmpty) {
+        atomicOr(&s[1], (q << 16) | g);
         break;
       }
-      if (atomicCAS(&hw[4 * b + 2], kEmpty, w) == kEmpty) {
-        hw[4 * b + 3] = (q << 16) | xb;
+      if (atomicCAS(&s[2], kEmpty, w) == kEmpty) {
+        atomicOr(&s[3], (q << 16) | g);
         break;
       }
+      atomicOr(&s[3], kPassed);
       b = hnext(b);
     }
     // counts exist only for Min-Count graphs: loaded for their selection
@@ -313,9 +335,9 @@ __device__ void tri_forward_eids(TriCtx& C, TriSmem& S, uint32_t ia, uint32_t ib
     if (!(S.fwd[i >> 5] & (1u << (i & 31)))) continue;
     const uint64_t j = (uint64_t)C.j0 + i;
     const uint32_t w = C.a.rcol[j];
-    const uint32_t xb = all_rows ? C.a.fstart[S.srow[i]] - C.D0 : 0u;
+    const uint32_t g = all_rows ? (C.a.fstart[S.srow[i]] - C.D0) << kRowTag : 0u;
     uint32_t qpos;
-    if (hlookup(S.hb, w, xb, qpos)) C.a.eid[j] = C.D0 + qpos;
+    if (hlookup(S.hb, w, g, qpos)) C.a.eid[j] = C.D0 + qpos;
   }
 }
 
@@ -354,7 +376,7 @@ __device__ __forceinline__ uint32_t tri_drain_eo(TriCtx& C, TriSmem& S, const ui
   uint4 ra = make_uint4(0u, 0u, 0u, 0u), rb = ra;
   if (lane < cnt) {
     const uint2 rec = q[(head + lane) % kQ];
-    const uint32_t k = rec.y >> 16, qpos = rec.y & 0xffffu;
+    const uint32_t k = rec.y >> 16, qpos = rec.y & kQposMask;
     const uint4 ie = S.ie[k];
     const uint32_t p_yw = ie.x + (rec.x - S.ie_pre[k]);
     const uint32_t ow = S.xold[qpos];
@@ -428,7 +450,7 @@ __device__ __forceinline__ uint32_t tri_drain(TriCtx& C, TriSmem* Sp, const uint
   uint32_t sel = 0;
   if (lane < cnt) {
     const uint2 rec = q[(head + lane) % kQ];
-    const uint32_t k = rec.y >> 16, qpos = rec.y & 0xffffu;
+    const uint32_t k = rec.y >> 16, qpos = rec.y & kQposMask;
     const uint4 ie = S.ie[k];
     const uint32_t p_yw = ie.x + (rec.x - S.ie_pre[k]);
     const uint32_t ow = S.xold[qpos];
@@ -504,7 +526,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     // in-edge of an Edge-Once round is not scanned
     const uint32_t beg = fe > fs && e < yr.y && !closed ? e + 1 : yr.y;
     cnt = yr.y - beg;
-    xtag = all_rows ? (fs - C.D0) : 0u;
+    xtag = all_rows ? (fs - C.D0) << kRowTag : 0u;
     S.ie[tid] = make_uint4(beg, x, c, r);
     S.ie_e[tid] = e;
     if (kGeneral) C.X->ie_cnt[tid] = C.op == SLIM_OP_MCTR ? C.a.tcount[e] : 0u;
@@ -565,7 +587,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     for (int u = 0; u < kUnroll; ++u) {
       const uint32_t base = wb + u * kWave;
       const uint32_t t = base + lane;
-      uint32_t k = kcur, b = c_bmp, g = c_tag;
+      uint32_t k = kcur, g = c_tag, p = c_bmp + t;  // p: DAG position of the item (edge {y,w})
       const uint32_t lim = base + kWave < we ? base + kWave : we;
       while (c_nxt < lim) {  // the next in-edge starts inside this window
         const uint32_t bound = c_nxt;
@@ -573,18 +595,19 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
         fetch(kcur);
         const bool after = t >= bound;
         k = after ? kcur : k;
-        b = after ? c_bmp : b;
+        p = after ? c_bmp + t : p;
         g = after ? c_tag : g;
       }
-      // a lane past the range gets row offset 0xffff, which no hashed entry
-      // has (offsets are below kHashCap): it never hits
+      // a lane past the range gets row tag kNoRow, which no hashed key has
+      // (row tags are multiples of 16): it never hits
       kk[u] = k;
-      xb[u] = t < we ? g : 0xffffu;
-      ad[u] = t < we ? b + t : 0u;  // DAG position of the item (the edge {y,w})
+      xb[u] = t < we ? g : kNoRow;
+      ad[u] = t < we ? p : 0u;
       wv[u] = C.a.dag_col[ad[u]];
     }
     // Probe window by window: the home bucket and the next one (four slots,
-    // read together); a key can only sit further on if both are full.  The
+    // read together); a key can only sit further on if an insertion went on
+    // past the second one (its kPassed bit).  The
     // SIMDs issue vector instructions in most cycles of this loop, so the
     // probe is written for few of them: one compare per slot key, the row
     // tag of the first slot holding w, and the rare cases (the same w in
@@ -592,9 +615,9 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     // which the exec mask skips when no lane takes them.
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const uint32_t bku = hbucket(wv[u], xb[u]);
-      const uint4 e = S.hb[bku];
-      const uint4 f = S.hb[bku + 1];  // adjacent: the spare bucket follows the last
+      const uint32_t bku = hhome(wv[u], xb[u]);
+      const uint4 e = hread(S.hb, bku);
+      const uint4 f = hread(S.hb, bku + (1u << kRowTag));  // adjacent: the spare bucket follows the last
       const uint32_t t = wb + u * kWave + lane, wq = wv[u], g = xb[u];
       const bool k0 = e.x == wq, k1 = e.z == wq, k2 = f.x == wq;
       uint32_t tsel = f.w;
@@ -604,8 +627,8 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
       const bool kany = (k0 | k1 | k2) || f.z == wq;
       const bool rowok = (tsel & 0xffffu) == g;
       bool hit = kany & rowok;
-      uint32_t qpos = tsel >> 16;
-      bool more = !kany & (e.z != kEmpty) & (f.z != kEmpty);
+      uint32_t qpos = tsel >> 16;  // kPassed may ride along in bit 15: masked where it is used
+      bool more = !kany & ((int32_t)f.w < 0);
       if (kany & !hit) {  // w is hashed for another row too: check all four slots
         const bool m0 = k0 & ((e.y & 0xffffu) == g);
         const bool m1 = k1 & ((e.w & 0xffffu) == g);
@@ -613,21 +636,21 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
         const bool m3 = (f.z == wq) & ((f.w & 0xffffu) == g);
         hit = m0 | m1 | m2 | m3;
         qpos = (m0 ? e.y : m1 ? e.w : m2 ? f.y : f.w) >> 16;
-        more = !hit & (e.z != kEmpty) & (f.z != kEmpty);
+        more = !hit & ((int32_t)f.w < 0);
       }
-      uint32_t bkt = bku + 1;
-      while (more) {  // both buckets full: keep probing (rare)
+      uint32_t bkt = bku + (1u << kRowTag);
+      while (more) {  // an insertion went on past both buckets: keep probing (rare)
         bkt = hnext(bkt);
-        const uint4 h = S.hb[bkt];
+        const uint4 h = hread(S.hb, bkt);
         const bool n0 = (h.x == wq) & ((h.y & 0xffffu) == g);
         const bool n1 = (h.z == wq) & ((h.w & 0xffffu) == g);
         hit = n0 | n1;
         qpos = (n0 ? h.y : h.w) >> 16;
-        more = !(n0 | n1) & (h.z != kEmpty);
+        more = !(n0 | n1) & ((int32_t)h.w < 0);
       }
       if constexpr (kCount) {  // one more triangle on each of its three edges
         if (hit) {
-          atomicAdd(&C.X->xcnt[qpos], 1u);
+          atomicAdd(&C.X->xcnt[qpos & kQposMask], 1u);
           atomicAdd(C.a.tcount + ad[u], 1u);
         }
         // {y,x}: the hits of one in-edge add together (a window rarely
