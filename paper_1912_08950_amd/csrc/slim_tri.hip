@@ -65,7 +65,6 @@ constexpr int kWavesPerEU = 2 * kTW / 4;  // two resident blocks per CU (LDS), f
 constexpr int kHashCap = 2048;       // out-list entries hashed per pass
 constexpr int kBuckets = 2048;       // hash buckets of two slots (load <= 1/2)
 constexpr int kBucketBits = 11;
-constexpr int kBatch = 320;          // in-edges per batch
 constexpr int kQ = 128;              // per-wave hit queue (records)
 #ifndef SLIM_TRI_UNROLL
 #define SLIM_TRI_UNROLL 8
@@ -74,10 +73,18 @@ constexpr int kUnroll = SLIM_TRI_UNROLL;  // windows of 64 items whose loads are
 constexpr uint32_t kEmpty = 0xffffffffu;
 constexpr uint32_t kDead = 0xffffffffu;  // Edge-Once list record of a decided triangle
 
-static_assert(kBatch <= kTB, "one thread per in-edge in the setup");
 static_assert(kTC <= kWave, "one wave scans the chunk sums");
 
+// In-edges per batch (kB) of each instantiation: as many as two blocks per CU
+// allow in LDS; the general and Edge-Once ones also keep per-in-edge counts
+// or bids (larger batches cut the per-batch setup and barriers).
+constexpr int kLdsPerBlock = 160 * 1024 / 2;
+template <int kMode>
+constexpr int kBatchOf = kMode == kModePlain ? 512 : (kMode == kModeEO ? 352 : 384);
+
+template <int kB>
 struct TriSmem {
+  static_assert(kB <= kTB, "one thread per in-edge in the setup");
   uint32_t srow[kTT];  // row of each tile entry (after the max-scan)
   uint32_t cmax[kTC];
   uint16_t bw[kTT];    // local indices of the tile's backward entries, in order
@@ -85,11 +92,11 @@ struct TriSmem {
   uint4 hb[kBuckets + 1];     // two slots {w, tag}; tag = (position in range << 16) | row tag
   uint32_t xold[kHashCap];    // original id of each hashed out-list entry
   uint32_t xbits[kHashCap / 32 + 2];
-  uint4 ie[kBatch];           // {scan begin, x rank, y old id, x old id}
-  uint32_t ie_pre[kBatch + 1];
-  uint32_t ie_e[kBatch];      // DAG position of (y,x) (kEmpty until found)
-  uint4 ie_scan[kBatch];      // {scan begin - item base, hash tag, next in-edge start, 0}
-  uint32_t ie_flag[(kBatch + 31) / 32];
+  uint4 ie[kB];           // {scan begin, x rank, y old id, x old id}
+  uint32_t ie_pre[kB + 1];
+  uint32_t ie_e[kB];      // DAG position of (y,x) (kEmpty until found)
+  uint4 ie_scan[kB];      // {scan begin - item base, hash tag, next in-edge start, 0}
+  uint32_t ie_flag[(kB + 31) / 32];
   union {
     uint32_t dpos[kHashCap];  // row start offset of each hashed position
     uint2 queue[kTW][kQ];     // hit records {item, (in-edge << 16) | position in range}
@@ -101,27 +108,26 @@ struct TriSmem {
   uint64_t red[2][kTW];
 };
 
+template <int kB>
+struct TriSmemPlain {
+  TriSmem<kB> s;
+};
 // LDS of the general instantiation: per-edge triangle counts of the hashed
 // range and of the batch's in-edges (accumulated in the counting pass, loaded
 // for the Min-Count selection).
-struct TriX {
-  uint32_t xcnt[kHashCap];
-  uint32_t ie_cnt[kBatch];
-};
-
-struct TriSmemPlain {
-  TriSmem s;
-};
+template <int kB>
 struct TriSmemGeneral {
-  TriSmem s;
-  TriX x;
+  TriSmem<kB> s;
+  uint32_t xcnt[kHashCap];
+  uint32_t ie_cnt[kB];
 };
 // LDS of the Edge-Once instantiation: the smallest bid on each in-edge of
 // the batch, written to the global minimum once per batch, and the smallest
 // priority word bid on each hashed out-list entry in the current pass.
+template <int kB>
 struct TriSmemEO {
-  TriSmem s;
-  uint64_t ie_key[kBatch];
+  TriSmem<kB> s;
+  uint64_t ie_key[kB];
   uint32_t xmin[kHashCap];
 };
 
@@ -214,8 +220,9 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Row of every entry of the tile [j0, j0 + kTT): srow[i] after the scan.
+template <int kB>
 __device__ void tri_tile_rows(const int64_t* row_off, int64_t j0, uint32_t lo, uint32_t hi,
-                              TriSmem& S) {
+                              TriSmem<kB>& S) {
   const int t = threadIdx.x, w = t / kWave, lane = lane_id();
   for (int i = t; i < kTT; i += kTB) S.srow[i] = 0;
   __syncthreads();
@@ -250,7 +257,8 @@ __device__ void tri_tile_rows(const int64_t* row_off, int64_t j0, uint32_t lo, u
 
 struct TriCtx {
   TriArgs a;
-  TriX* X;        // general instantiation only
+  uint32_t* xcnt;    // general instantiation only: per-edge counts of the hashed range
+  uint32_t* ie_cnt;  //   and of the batch's in-edges
   uint64_t* ie_key;  // Edge-Once instantiation only
   uint32_t* xmin;    // Edge-Once instantiation only
   uint32_t cap;   // out-list entries hashed per pass (<= kHashCap)
@@ -270,7 +278,8 @@ struct TriCtx {
 
 // Hash the out-list entries [D0, D0 + len) under key (w, row tag); the row
 // start offset comes from dpos (all rows of the tile) or is 0 (one row).
-__device__ void tri_build_hash(TriCtx& C, TriSmem& S, uint32_t len, bool use_dpos) {
+template <int kB>
+__device__ void tri_build_hash(TriCtx& C, TriSmem<kB>& S, uint32_t len, bool use_dpos) {
   for (int i = threadIdx.x; i < kBuckets + 1; i += kTB)
     S.hb[i] = make_uint4(kEmpty, 0u, kEmpty, 0u);
   for (int i = threadIdx.x; i < kHashCap / 32 + 2; i += kTB) S.xbits[i] = 0;
@@ -303,17 +312,18 @@ __device__ void tri_build_hash(TriCtx& C, TriSmem& S, uint32_t len, bool use_dpo
     }
     // counts exist only for Min-Count graphs: loaded for their selection
     // pass, zeroed for their counting pass (other operations never read them)
-    if (C.X) C.X->xcnt[q] = C.a.pass == 1 && C.op == SLIM_OP_MCTR ? C.a.tcount[C.D0 + q] : 0u;
+    if (C.xcnt) C.xcnt[q] = C.a.pass == 1 && C.op == SLIM_OP_MCTR ? C.a.tcount[C.D0 + q] : 0u;
   }
   C.hlen = len;
   __syncthreads();
 }
 
-__device__ void tri_flush_xbits(TriCtx& C, TriSmem& S) {
+template <int kB>
+__device__ void tri_flush_xbits(TriCtx& C, TriSmem<kB>& S) {
   __syncthreads();
-  if (C.X && C.a.pass == 0) {  // counting pass: add the (x,w) counts of the range
+  if (C.xcnt && C.a.pass == 0) {  // counting pass: add the (x,w) counts of the range
     for (uint32_t q = threadIdx.x; q < C.hlen; q += kTB) {
-      const uint32_t v = C.X->xcnt[q];
+      const uint32_t v = C.xcnt[q];
       if (v) atomicAdd(C.a.tcount + C.D0 + q, v);
     }
   } else {
@@ -328,7 +338,8 @@ __device__ void tri_flush_xbits(TriCtx& C, TriSmem& S) {
 // Forward entries among tile entries [ia, ib): their edge is in out(x) of the
 // entry's own row, so the DAG position comes from the hash (a miss means the
 // entry lies in another pass of a split row).
-__device__ void tri_forward_eids(TriCtx& C, TriSmem& S, uint32_t ia, uint32_t ib,
+template <int kB>
+__device__ void tri_forward_eids(TriCtx& C, TriSmem<kB>& S, uint32_t ia, uint32_t ib,
                                  bool all_rows) {
   if (C.hlen == 0) return;
   for (uint32_t i = ia + threadIdx.x; i < ib; i += kTB) {
@@ -343,7 +354,8 @@ __device__ void tri_forward_eids(TriCtx& C, TriSmem& S, uint32_t ia, uint32_t ib
 
 // Marks the edge of triangle (y,x,w) that does not contain vertex `excl`
 // (union ids: c = y, u0 = x, ow = w).
-__device__ __forceinline__ void tri_mark(uint8_t* marks, TriSmem& S, uint32_t excl, uint32_t c,
+template <int kB>
+__device__ __forceinline__ void tri_mark(uint8_t* marks, TriSmem<kB>& S, uint32_t excl, uint32_t c,
                                          uint32_t ow, uint32_t k, uint32_t qpos, uint32_t D0,
                                          uint32_t p_yw) {
   if (excl == ow) {  // edge {y,x}: flag of the in-edge
@@ -368,7 +380,8 @@ __device__ __forceinline__ void eo_bid(uint64_t* p, uint64_t key) {
 // bidding pass that starts the triangle list, every bidding triangle is
 // also appended to the list (one counter atomic per wave).  Returns 1 in
 // lanes that bid.
-__device__ __forceinline__ uint32_t tri_drain_eo(TriCtx& C, TriSmem& S, const uint2* q,
+template <int kB>
+__device__ __forceinline__ uint32_t tri_drain_eo(TriCtx& C, TriSmem<kB>& S, const uint2* q,
                                                  uint32_t head, uint32_t cnt) {
   const uint32_t lane = lane_id();
   uint32_t res = 0;
@@ -440,12 +453,12 @@ __device__ __forceinline__ uint32_t tri_drain_eo(TriCtx& C, TriSmem& S, const ui
 
 // Hash, select and mark the queued hits q[head .. head + cnt) (cnt <= 64);
 // one lane per hit.  Returns 1 in lanes whose triangle was selected.
-template <int kMode>
-__device__ __forceinline__ uint32_t tri_drain(TriCtx& C, TriSmem* Sp, const uint2* q,
+template <int kMode, int kB>
+__device__ __forceinline__ uint32_t tri_drain(TriCtx& C, TriSmem<kB>* Sp, const uint2* q,
                                               uint32_t head, uint32_t cnt) {
   constexpr bool kGeneral = kMode == kModeGeneral, kEO = kMode == kModeEO;
   if constexpr (kEO) return tri_drain_eo(C, *Sp, q, head, cnt);
-  TriSmem& S = *Sp;
+  TriSmem<kB>& S = *Sp;
   const uint32_t lane = lane_id();
   uint32_t sel = 0;
   if (lane < cnt) {
@@ -469,8 +482,8 @@ __device__ __forceinline__ uint32_t tri_drain(TriCtx& C, TriSmem* Sp, const uint
         uint32_t t[3];
 #pragma unroll
         for (int e = 0; e < 3; ++e)
-          t[e] = excl[e] == ow ? C.X->ie_cnt[k]
-                               : (excl[e] == c ? C.X->xcnt[qpos] : C.a.tcount[p_yw]);
+          t[e] = excl[e] == ow ? C.ie_cnt[k]
+                               : (excl[e] == c ? C.xcnt[qpos] : C.a.tcount[p_yw]);
         const uint32_t tmin = min(t[0], min(t[1], t[2]));
         const uint32_t nt = (t[0] == tmin) + (t[1] == tmin) + (t[2] == tmin);
         uint32_t pick = __umulhi(w1, nt), e = 0;
@@ -493,8 +506,8 @@ __device__ __forceinline__ uint32_t tri_drain(TriCtx& C, TriSmem* Sp, const uint
 }
 
 // Process the in-edges bw[b0, b1) of the tile against the current hash.
-template <int kMode>
-__device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool all_rows) {
+template <int kMode, int kB>
+__device__ void tri_batch(TriCtx& C, TriSmem<kB>& S, uint32_t b0, uint32_t b1, bool all_rows) {
   constexpr bool kGeneral = kMode == kModeGeneral, kCount = kMode == kModeCount;
   const int tid = threadIdx.x;
   const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -529,11 +542,11 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
     xtag = all_rows ? (fs - C.D0) << kRowTag : 0u;
     S.ie[tid] = make_uint4(beg, x, c, r);
     S.ie_e[tid] = e;
-    if (kGeneral) C.X->ie_cnt[tid] = C.op == SLIM_OP_MCTR ? C.a.tcount[e] : 0u;
-    if (kCount) C.X->ie_cnt[tid] = 0u;
+    if (kGeneral) C.ie_cnt[tid] = C.op == SLIM_OP_MCTR ? C.a.tcount[e] : 0u;
+    if (kCount) C.ie_cnt[tid] = 0u;
     bmp = beg;
   }
-  if ((uint32_t)tid < (kBatch + 31) / 32) S.ie_flag[tid] = 0;
+  if ((uint32_t)tid < (kB + 31) / 32) S.ie_flag[tid] = 0;
   if (C.ie_key && (uint32_t)tid < nin) C.ie_key[tid] = ~0ull;
   {  // block exclusive scan of cnt into ie_pre; scan records {beg - pre, tag, next start}
     const uint64_t incl = wave_incl_sum64(cnt);
@@ -650,7 +663,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
       }
       if constexpr (kCount) {  // one more triangle on each of its three edges
         if (hit) {
-          atomicAdd(&C.X->xcnt[qpos & kQposMask], 1u);
+          atomicAdd(&C.xcnt[qpos & kQposMask], 1u);
           atomicAdd(C.a.tcount + ad[u], 1u);
         }
         // {y,x}: the hits of one in-edge add together (a window rarely
@@ -660,7 +673,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
           const int src = __builtin_ctzll(rem);
           const uint32_t ks = __shfl(kk[u], src, kWave);
           const uint64_t same = __ballot(hit && kk[u] == ks);
-          if ((int)lane == src) atomicAdd(&C.X->ie_cnt[ks], (uint32_t)__popcll(same));
+          if ((int)lane == src) atomicAdd(&C.ie_cnt[ks], (uint32_t)__popcll(same));
           rem &= ~same;
         }
         continue;
@@ -673,7 +686,7 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
         qcnt += __popcll(bal);
         if (qcnt >= (uint32_t)kWave) {
           wave_sync();
-          C.n_sel += tri_drain<kMode>(C, &S, q, qhead, kWave);
+          C.n_sel += tri_drain<kMode, kB>(C, &S, q, qhead, kWave);
           C.n_tri += 1;
           qhead = (qhead + kWave) % kQ;
           qcnt -= kWave;
@@ -683,13 +696,13 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
   }
   if (qcnt) {
     wave_sync();
-    C.n_sel += tri_drain<kMode>(C, &S, q, qhead, qcnt);
+    C.n_sel += tri_drain<kMode, kB>(C, &S, q, qhead, qcnt);
     C.n_tri += lane < qcnt ? 1 : 0;
   }
   __syncthreads();
   // ---- finish: (y,x) marks, or the (y,x) counts of the counting pass
   if (kCount) {
-    if ((uint32_t)tid < nin && C.X->ie_cnt[tid]) atomicAdd(C.a.tcount + S.ie_e[tid], C.X->ie_cnt[tid]);
+    if ((uint32_t)tid < nin && C.ie_cnt[tid]) atomicAdd(C.a.tcount + S.ie_e[tid], C.ie_cnt[tid]);
   } else if ((uint32_t)tid < nin && (S.ie_flag[tid >> 5] & (1u << (tid & 31)))) {
     mark_set(C.a.marks, S.ie_e[tid]);
   }
@@ -702,7 +715,8 @@ __device__ void tri_batch(TriCtx& C, TriSmem& S, uint32_t b0, uint32_t b1, bool 
 // Edge-Once bids add the undecided triangles to the round's counter (and,
 // in the first round, T and the selected count to the graph's counters);
 // acceptance passes report nothing.
-__device__ void tri_flush_counts(TriCtx& C, TriSmem& S, uint32_t g) {
+template <int kB>
+__device__ void tri_flush_counts(TriCtx& C, TriSmem<kB>& S, uint32_t g) {
   const int tid = threadIdx.x, w = tid / kWave;
   const uint64_t s0 = wave_sum64(C.n_tri), s1 = wave_sum64(C.n_sel);
   const bool first = C.a.pass < 2 || (C.a.pass == 2 && C.a.round == 1);
@@ -736,15 +750,21 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     TriArgs a, uint32_t* tile_ctr, uint32_t cap) {
   constexpr bool kGeneral = kMode == kModeGeneral, kEO = kMode == kModeEO;
   constexpr bool kCount = kMode == kModeCount;
-  __shared__ std::conditional_t<kGeneral || kCount, TriSmemGeneral,
-                                std::conditional_t<kEO, TriSmemEO, TriSmemPlain>> SS;
-  TriSmem& S = SS.s;
+  constexpr int kB = kBatchOf<kMode>;
+  using Smem = std::conditional_t<kGeneral || kCount, TriSmemGeneral<kB>,
+                                  std::conditional_t<kEO, TriSmemEO<kB>, TriSmemPlain<kB>>>;
+  static_assert(sizeof(Smem) <= kLdsPerBlock, "two blocks per CU share the LDS");
+  __shared__ Smem SS;
+  TriSmem<kB>& S = SS.s;
   TriCtx C;
   C.a = a;
-  if constexpr (kGeneral || kCount)
-    C.X = &SS.x;
-  else
-    C.X = nullptr;
+  if constexpr (kGeneral || kCount) {
+    C.xcnt = SS.xcnt;
+    C.ie_cnt = SS.ie_cnt;
+  } else {
+    C.xcnt = nullptr;
+    C.ie_cnt = nullptr;
+  }
   if constexpr (kEO) {
     C.ie_key = SS.ie_key;
     C.xmin = SS.xmin;
@@ -955,8 +975,8 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
       C.D0 = pD0;
       tri_build_hash(C, S, plen, all_rows);
       if (!C.eo_later) tri_forward_eids(C, S, pfa, pfb, all_rows);
-      for (uint32_t b0 = pb0; b0 < pb1; b0 += kBatch)
-        tri_batch<kMode>(C, S, b0, b0 + kBatch < pb1 ? b0 + kBatch : pb1, all_rows);
+      for (uint32_t b0 = pb0; b0 < pb1; b0 += kB)
+        tri_batch<kMode, kB>(C, S, b0, b0 + kB < pb1 ? b0 + kB : pb1, all_rows);
       tri_flush_xbits(C, S);
     }
     if (kEO) {  // record the round in which the tile still bid
