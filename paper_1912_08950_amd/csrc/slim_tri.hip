@@ -73,7 +73,7 @@ constexpr int kUnroll = SLIM_TRI_UNROLL;  // windows of 64 items whose loads are
 constexpr uint32_t kEmpty = 0xffffffffu;
 constexpr uint32_t kDead = 0xffffffffu;  // Edge-Once list record of a decided triangle
 
-static_assert(kTC <= kWave, "one wave scans the chunk sums");
+static_assert(kTC <= kWave && kHashCap / kWave <= kWave, "one wave scans the chunk sums and maxima");
 
 // In-edges per batch (kB) of each instantiation: as many as two blocks per CU
 // allow in LDS; the general and Edge-Once ones also keep per-in-edge counts
@@ -102,7 +102,7 @@ struct TriSmem {
     uint2 queue[kTW][kQ];     // hit records {item, (in-edge << 16) | position in range}
   } u;
   uint32_t wsum[kTW];
-  uint32_t cbase[kTC];
+  uint32_t cbase[kHashCap / kWave];  // per chunk: bw slots of the tile, or row offset maxima of the hashed range
   uint64_t cmask[kTC];
   uint32_t bcast[4];
   uint64_t red[2][kTW];
