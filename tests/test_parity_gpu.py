@@ -443,6 +443,35 @@ def test_dag_rows_of_every_sort_class(slim, p):
     assert_same(gpu_run_op(slim, g, "eotr", p, 3), oracle_run_x(g, "eotr", p, 3), "sort classes eotr")
 
 
+def double_star(n_leaves):
+    """Vertices 0 and 1 joined to each other and to every leaf 2..n+1: the n
+    triangles {0,1,leaf} are all found from vertex 0's row, whose n in-edges
+    (leaf, 0) each scan one item, the edge to vertex 1."""
+    leaves = range(2, n_leaves + 2)
+    pairs = [(0, 1)] + [(0, i) for i in leaves] + [(1, i) for i in leaves]
+    return gg.from_pairs(n_leaves + 2, pairs, f"double_star{n_leaves}")
+
+
+# In-edges per batch are 512 (p-1), 384 (p-2, Min-Count) and 352 (Edge-Once).
+# A double star puts its n scanning in-edges in one batch run of a tile; the
+# wheels' second tile holds 352, 353, 384, 385, 512 and 513 in-edges.
+BATCH_EDGE_GRAPHS = ([double_star(n) for n in (351, 352, 353, 383, 384, 385, 511, 512, 513,
+                                               1023, 1024, 1025)]
+                     + [wheel(n) for n in (1041, 1042, 1089, 1090, 1281, 1282)])
+
+
+@pytest.mark.parametrize("op", ["tr", "tr2", "mctr", "eotr"])
+def test_batch_boundaries(slim, op):
+    """Tiles whose in-edges fill each instantiation's batch exactly, or by one."""
+    for g in BATCH_EDGE_GRAPHS:
+        for p, seed in ((0.5, 1), (1.0, 2)):
+            if op == "tr":
+                got, want = gpu_run(slim, g, op, p, seed), oracle_run(g, op, p, seed)
+            else:
+                got, want = gpu_run_op(slim, g, op, p, seed), oracle_run_x(g, op, p, seed)
+            assert_same(got, want, f"{g.name} {op} p={p} seed={seed}")
+
+
 # ------------------------------------------------- spectral sparsification
 
 def oracle_spectral(g, ups, seed):
